@@ -1,0 +1,431 @@
+"""Pins of the oracle's volume operator and of the whole cRKFR step:
+entropy and conservation identities of flux differencing (Section 3),
+the central flux recovering D f (eq:flux.dev), free-stream preservation,
+conservation of totals, pressure equilibrium of the density wave with the
+EC/KEP flux, the one-stage tableau reducing to a forward-Euler FR step,
+zero entropy production of the semi-discrete EC scheme, design-order
+convergence, and the blending limiter's special cases."""
+import numpy as np
+import pytest
+
+from paper_2604_02125_amd import inputs
+
+
+def _rand_elem_euler(rng, np_, dim, g=1.4):
+    rho = rng.uniform(0.5, 2.0, np_)
+    v = rng.uniform(-1, 1, (dim, np_))
+    p = rng.uniform(0.5, 2.0, np_)
+    u = np.stack([rho, *(rho * v), p / (g - 1) + 0.5 * rho * (v * v).sum(0)])
+    return u.T.copy()   # [node, v]
+
+
+def _rand_elem_mhd(rng, np_, g=5.0 / 3.0):
+    rho = rng.uniform(0.5, 2.0, np_)
+    v = rng.uniform(-1, 1, (3, np_))
+    B = rng.uniform(-1, 1, (3, np_))
+    psi = rng.uniform(-0.3, 0.3, np_)
+    p = rng.uniform(0.5, 2.0, np_)
+    E = p / (g - 1) + 0.5 * rho * (v * v).sum(0) + 0.5 * (B * B).sum(0) + 0.5 * psi ** 2
+    return np.stack([rho, *(rho * v), E, *B, psi]).T.copy()
+
+
+def _lines(N, dim):
+    """(direction, list of node indices along the line) for every line."""
+    n = N + 1
+    if dim == 1:
+        return [(0, list(range(n)))]
+    out = []
+    for j in range(n):
+        out.append((0, [j * n + i for i in range(n)]))
+    for i in range(n):
+        out.append((1, [j * n + i for j in range(n)]))
+    return out
+
+
+def _wq(orc, N, dim):
+    _, w = orc.gll(N)
+    return w if dim == 1 else np.outer(w, w).ravel()   # index j*n+i -> w_j w_i
+
+
+CASES = [(1, 3, 0, 2), (2, 3, 0, 2), (2, 4, 0, 2), (2, 2, 0, 2), (2, 3, 1, 3), (2, 4, 1, 3)]
+
+
+@pytest.mark.parametrize("dim,N,eq,vol", CASES)
+def test_element_entropy_identity(orc, dim, N, eq, vol):
+    """sum_p w_p w(u_p).R_p = sum over lines of the transverse weight times
+    (q_d(u_last) - q_d(u_first))/dx_d, for EC two-point fluxes (with the local
+    Powell/GLM term for MHD)."""
+    kw = dict(dim=dim, N=N, eq=eq, vol_flux=vol, nx=4, ny=4, x1=1.0, y1=2.0)
+    if eq == 1:
+        kw.update(gamma=5.0 / 3.0, ch=0.8)
+    prob = orc.Problem(**kw)
+    rng = np.random.default_rng(11)
+    _, w = orc.gll(N)
+    dx = [1.0 / 4, 2.0 / 4]
+    for _ in range(5):
+        ue = _rand_elem_euler(rng, prob.nnode, dim) if eq == 0 else _rand_elem_mhd(rng, prob.nnode)
+        R = orc.volume_residual(prob, ue)
+        wq = _wq(orc, N, dim)
+        lhs = sum(wq[p] * orc.entropy_vars(prob, ue[p]) @ R[p] for p in range(prob.nnode))
+        rhs = 0.0
+        for d, line in _lines(N, dim):
+            tw = 1.0 if dim == 1 else w[line[0] // (N + 1)] if d == 0 else w[line[0] % (N + 1)]
+            rhs += tw * (orc.entropy_flux(prob, d, ue[line[-1]]) - orc.entropy_flux(prob, d, ue[line[0]])) / dx[d]
+        scale = sum(wq[p] * np.abs(orc.entropy_vars(prob, ue[p])) @ np.abs(R[p]) for p in range(prob.nnode))
+        assert abs(lhs - rhs) < 1e-13 * scale
+
+
+def test_element_entropy_identity_fails_for_kg(orc):
+    prob = orc.Problem(dim=2, N=3, vol_flux=orc.VOL_KG)
+    rng = np.random.default_rng(12)
+    ue = _rand_elem_euler(rng, 16, 2)
+    R = orc.volume_residual(prob, ue)
+    _, w = orc.gll(3)
+    wq = _wq(orc, 3, 2)
+    lhs = sum(wq[p] * orc.entropy_vars(prob, ue[p]) @ R[p] for p in range(16))
+    rhs = 0.0
+    for d, line in _lines(3, 2):
+        tw = w[line[0] // 4] if d == 0 else w[line[0] % 4]
+        rhs += tw * (orc.entropy_flux(prob, d, ue[line[-1]]) - orc.entropy_flux(prob, d, ue[line[0]])) * 4
+    assert abs(lhs - rhs) > 1e-3
+
+
+@pytest.mark.parametrize("dim,N,vol", [(1, 3, 0), (1, 3, 1), (1, 3, 2), (2, 3, 1), (2, 4, 2), (2, 2, 0)])
+def test_element_conservation_identity(orc, dim, N, vol):
+    """sum_p w_p R_p = sum over lines of (f_d(u_last) - f_d(u_first))/dx_d."""
+    prob = orc.Problem(dim=dim, N=N, vol_flux=vol, nx=4, ny=4)
+    rng = np.random.default_rng(13)
+    _, w = orc.gll(N)
+    ue = _rand_elem_euler(rng, prob.nnode, dim)
+    R = orc.volume_residual(prob, ue)
+    wq = _wq(orc, N, dim)
+    lhs = (wq[:, None] * R).sum(0)
+    rhs = np.zeros(prob.nvar)
+    for d, line in _lines(N, dim):
+        tw = 1.0 if dim == 1 else w[line[0] // (N + 1)] if d == 0 else w[line[0] % (N + 1)]
+        rhs += tw * (orc.phys_flux(prob, d, ue[line[-1]]) - orc.phys_flux(prob, d, ue[line[0]])) * 4
+    assert np.max(np.abs(lhs - rhs)) < 1e-12 * (1 + np.max(np.abs(rhs)))
+
+
+@pytest.mark.parametrize("dim,N", [(1, 3), (2, 3), (2, 4)])
+def test_central_flux_recovers_D_f(orc, dim, N):
+    """With f_S = (f_p + f_q)/2 flux differencing equals sum_q D_pq f_q (eq:flux.dev)."""
+    prob = orc.Problem(dim=dim, N=N, vol_flux=orc.VOL_CENTRAL, nx=2, ny=5)
+    rng = np.random.default_rng(14)
+    ue = _rand_elem_euler(rng, prob.nnode, dim)
+    R = orc.volume_residual(prob, ue)
+    D = orc.diffmat(N)
+    expect = np.zeros_like(ue)
+    dx = [1.0 / 2, 1.0 / 5]
+    for d, line in _lines(N, dim):
+        F = np.array([orc.phys_flux(prob, d, ue[p]) for p in line])
+        expect[line] += (D @ F) / dx[d]
+    assert np.max(np.abs(R - expect)) < 1e-12 * np.max(np.abs(expect))
+
+
+# ---------------------------------------------------------------- whole step
+def _const_state(prob, rng):
+    u0 = _rand_elem_euler(rng, 1, prob.dim)[0]
+    return np.broadcast_to(u0[:, None, None], prob.shape).copy()
+
+
+@pytest.mark.parametrize("dim,N,vol,lim", [(1, 3, 2, 0), (2, 3, 1, 0), (2, 3, 1, 2), (2, 4, 2, 0), (1, 2, 1, 2)])
+def test_free_stream(orc, dim, N, vol, lim):
+    prob = orc.Problem(dim=dim, N=N, vol_flux=vol, limiter=lim, nx=5, ny=3)
+    u = _const_state(prob, np.random.default_rng(15))
+    alpha = np.full(prob.nelem, 0.3) if lim else None
+    dt = orc.compute_dt(prob, u)
+    un, _ = orc.crk_step(prob, u, dt, alpha)
+    assert np.max(np.abs(un - u)) < 1e-13 * np.max(np.abs(u))
+
+
+def test_dt_closed_form(orc):
+    # rho = 1, v = 0, p = 1/gamma -> c = 1; dt = CFL / ((N+1) (1/dx + 1/dy))
+    prob = orc.Problem(dim=2, N=3, nx=8, ny=4, cfl=0.4)
+    u = np.zeros(prob.shape)
+    u[0] = 1.0
+    u[3] = (1 / 1.4) / 0.4
+    assert abs(orc.compute_dt(prob, u) - 0.4 / (4 * (8 + 4))) < 1e-15
+
+
+def _khi(orc, prob):
+    xi, _ = orc.gll(prob.N)
+    return inputs.kelvin_helmholtz(prob.nx, prob.ny, xi)
+
+
+@pytest.mark.parametrize("lim", [0, 1])
+def test_conservation_of_totals(orc, lim):
+    prob = orc.Problem(dim=2, N=3, nx=8, ny=8, x0=-1, x1=1, y0=-1, y1=1, vol_flux=orc.VOL_KG, limiter=lim)
+    u = inputs.perturb(_khi(orc, prob), 3, 1e-2)
+    t0 = orc.diagnostics(prob, u)["totals"]
+    for _ in range(3):
+        u, a = orc.crk_step(prob, u, orc.compute_dt(prob, u))
+    t1 = orc.diagnostics(prob, u)["totals"]
+    assert np.max(np.abs(t1 - t0) / np.maximum(np.abs(t0), 1.0)) < 1e-14
+    if lim:
+        assert a.max() > 0.0        # the blending limiter is active on this state
+
+
+def test_mhd_conserves_mass(orc):
+    xi, _ = orc.gll(3)
+    prob = orc.Problem(dim=2, N=3, nx=6, ny=6, eq=orc.MHD, gamma=5 / 3, vol_flux=orc.VOL_DERIGS)
+    u = inputs.orszag_tang(6, 6, xi)
+    prob.ch = orc.compute_ch(prob, u)
+    t0 = orc.diagnostics(prob, u)["totals"]
+    u1, _ = orc.crk_step(prob, u, orc.compute_dt(prob, u))
+    t1 = orc.diagnostics(prob, u1)["totals"]
+    assert abs(t1[0] - t0[0]) < 1e-14 * abs(t0[0])
+    assert np.max(np.abs(u1 - u)) > 1e-6
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_density_wave_pressure_equilibrium(orc, dim):
+    """Constant velocity and pressure are preserved exactly (up to rounding)
+    by the cRKFR step with the EC/KEP (Ranocha) volume flux and Rusanov
+    interfaces; the Kennedy-Gruber flux does not have this property."""
+    N = 3
+    xi, _ = orc.gll(N)
+    if dim == 1:
+        prob = orc.Problem(dim=1, N=N, nx=16, vol_flux=orc.VOL_RANOCHA)
+        u = inputs.density_wave_1d(16, xi)
+        vel = [0.1]
+    else:
+        prob = orc.Problem(dim=2, N=N, nx=6, ny=6, vol_flux=orc.VOL_RANOCHA)
+        u = inputs.density_wave_2d(6, 6, xi)
+        vel = [0.1, 0.2]
+
+    def dev(u):
+        rho = u[0]
+        dv = max(np.max(np.abs(u[1 + k] / rho - vel[k])) for k in range(dim))
+        p = (0.4) * (u[dim + 1] - 0.5 * sum(u[1 + k] ** 2 for k in range(dim)) / rho)
+        return dv, np.max(np.abs(p - 20.0))
+
+    uk = u.copy()
+    for _ in range(10):
+        u, _ = orc.crk_step(prob, u, orc.compute_dt(prob, u))
+    dv, dp = dev(u)
+    assert dv < 1e-13 and dp < 1e-11
+    prob.vol_flux = orc.VOL_KG
+    for _ in range(10):
+        uk, _ = orc.crk_step(prob, uk, orc.compute_dt(prob, uk))
+    assert dev(uk)[1] > 1e-6
+
+
+@pytest.mark.parametrize("dim,N,eq,vol", [(1, 3, 0, 2), (2, 3, 0, 1), (2, 2, 0, 2), (2, 3, 1, 3)])
+def test_one_stage_is_forward_euler_fr(orc, dim, N, eq, vol):
+    """s = 1, b = 1: U = u^n and F = f(u^n), so the cRKFR step is a forward
+    Euler step of the FR semi-discretisation; the latter is written with the
+    g2 correction derivatives from Radau polynomials, not with the lifting."""
+    xi, _ = orc.gll(N)
+    kw = dict(dim=dim, N=N, eq=eq, vol_flux=vol, nx=5, ny=4, A=orc.EULER1_A, b=orc.EULER1_B)
+    if eq == 1:
+        kw.update(gamma=5 / 3)
+        u = inputs.random_smooth_mhd(5, 4, xi, seed=5)
+    else:
+        u = inputs.random_smooth_euler(5, 4, xi, seed=5, dim=dim)
+    prob = orc.Problem(**kw)
+    if eq == 1:
+        prob.ch = orc.compute_ch(prob, u)
+    dt = orc.compute_dt(prob, u)
+    u1, _ = orc.crk_step(prob, u, dt)
+    ref = u + dt * orc.fr_rhs(prob, u)
+    assert np.max(np.abs(u1 - ref)) < 1e-13 * np.max(np.abs(u))
+    assert np.max(np.abs(u1 - u)) > 1e-5
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_semidiscrete_ec_entropy_rate_zero(orc, dim):
+    """EC volume flux + EC surface flux on a periodic mesh: dS/dt = 0."""
+    xi, w = orc.gll(3)
+    prob = orc.Problem(dim=dim, N=3, nx=5, ny=4, vol_flux=orc.VOL_RANOCHA)
+    # nodal noise makes the traces of neighbouring elements differ
+    u = inputs.perturb(inputs.random_smooth_euler(5, 4, xi, seed=7, dim=dim, amp=0.3), 8, 1e-2)
+    wq = _wq(orc, 3, dim)
+    for surf, small in ((orc.SURF_EC, True), (orc.SURF_RUSANOV, False)):
+        r = orc.fr_rhs(prob, u, surf)
+        rate, scale = 0.0, 0.0
+        for e in range(prob.nelem):
+            for p in range(prob.nnode):
+                wv = orc.entropy_vars(prob, u[:, e, p])
+                rate += wq[p] * wv @ r[:, e, p]
+                scale += wq[p] * np.abs(wv) @ np.abs(r[:, e, p])
+        if small:
+            assert abs(rate) < 1e-13 * scale
+        else:
+            assert rate < -1e-6 * scale   # Rusanov interfaces dissipate entropy
+
+
+def _density_wave_errors(orc, N, vol, nxs, T):
+    xi, w = orc.gll(N)
+    errs = []
+    for nx in nxs:
+        prob = orc.Problem(dim=1, N=N, nx=nx, vol_flux=vol)
+        u = inputs.density_wave_1d(nx, xi)
+        nsteps = int(np.ceil(T / orc.compute_dt(prob, u)))
+        for _ in range(nsteps):
+            u, _ = orc.crk_step(prob, u, T / nsteps)
+        ex = inputs.density_wave_1d(nx, xi, t=T)
+        errs.append(np.sqrt(np.sum(w[None, :] * (u[0] - ex[0]) ** 2) / nx))
+    return np.array(errs), np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+
+
+def test_density_wave_convergence(orc):
+    """Design-order (N+1) convergence of the cRKFR step (N=3, RK4) on the
+    smooth density wave at t = 0.5, central and Ranocha volume fluxes.  With
+    rho_min = 0.02 the EC flux is pre-asymptotic on coarse meshes, so its
+    rate is taken on the two finest meshes."""
+    errs, orders = _density_wave_errors(orc, 3, orc.VOL_CENTRAL, (8, 16, 32), 0.5)
+    assert orders.min() > 3.8, (errs, orders)
+    errs, orders = _density_wave_errors(orc, 3, orc.VOL_RANOCHA, (32, 64), 0.5)
+    assert orders.min() > 3.7 and errs[-1] < 1e-5, (errs, orders)
+
+
+def test_rkfr_multistage_conserves_and_converges(orc):
+    """Standard multi-stage RKFR (eq:rkfr.non.cons) on the same operators:
+    conservative, and of order N+1 on the density wave (central flux)."""
+    xi, w = orc.gll(3)
+    prob = orc.Problem(dim=2, N=3, nx=4, ny=4, vol_flux=orc.VOL_KG)
+    u = inputs.perturb(inputs.random_smooth_euler(4, 4, xi, seed=3), 4, 1e-2)
+    u1 = orc.rkfr_step(prob, u, orc.compute_dt(prob, u))
+    t0, t1 = orc.diagnostics(prob, u)["totals"], orc.diagnostics(prob, u1)["totals"]
+    assert np.max(np.abs(t1 - t0)) < 1e-14 * np.max(np.abs(t0))
+    errs = []
+    T = 0.5
+    for nx in (8, 16):
+        prob = orc.Problem(dim=1, N=3, nx=nx, vol_flux=orc.VOL_CENTRAL)
+        u = inputs.density_wave_1d(nx, xi)
+        n = int(np.ceil(T / orc.compute_dt(prob, u)))
+        for _ in range(n):
+            u = orc.rkfr_step(prob, u, T / n)
+        errs.append(np.sqrt(np.sum(w[None, :] * (u[0] - inputs.density_wave_1d(nx, xi, t=T)[0]) ** 2) / nx))
+    assert np.log2(errs[0] / errs[1]) > 3.8
+
+
+# ---------------------------------------------------------------- blending
+def test_blending_alpha_zero_is_high_order(orc):
+    prob = orc.Problem(dim=2, N=3, nx=6, ny=6, x0=-1, x1=1, y0=-1, y1=1, vol_flux=orc.VOL_KG)
+    u = _khi(orc, prob)
+    dt = orc.compute_dt(prob, u)
+    ref, _ = orc.crk_step(prob, u, dt)
+    prob.limiter = orc.LIM_BLEND_GIVEN
+    got, _ = orc.crk_step(prob, u, dt, np.zeros(prob.nelem))
+    assert np.max(np.abs(got - ref)) < 1e-15 * np.max(np.abs(u))
+
+
+def _subcell_fv(orc, prob, u, dt):
+    """Textbook first-order finite volumes with Rusanov fluxes on the periodic
+    grid of GLL subcells (cell widths w_k dx), written on global index arrays."""
+    N = prob.N
+    n = N + 1
+    _, w = orc.gll(N)
+    M = prob.nvar
+    if prob.dim == 1:
+        U = u.transpose(1, 2, 0).reshape(-1, M)            # [cell, v]
+        widths = np.tile(w, prob.nx) * (prob.x1 - prob.x0) / prob.nx
+        F = np.array([orc.phys_flux(prob, 0, c) for c in U])
+        lam = np.array([orc.wave_speed(prob, 0, c) for c in U])
+        Ur, Fr, lr = np.roll(U, -1, 0), np.roll(F, -1, 0), np.roll(lam, -1)
+        fr = 0.5 * (F + Fr) - 0.5 * np.maximum(lam, lr)[:, None] * (Ur - U)    # right face of cell c
+        fl = np.roll(fr, 1, 0)
+        return (U - dt / widths[:, None] * (fr - fl)).reshape(prob.nx, n, M).transpose(2, 0, 1)
+    nx, ny = prob.nx, prob.ny
+    G = u.reshape(M, ny, nx, n, n).transpose(1, 3, 2, 4, 0).reshape(ny * n, nx * n, M)   # [Y, X, v]
+    wx = np.tile(w, nx) * (prob.x1 - prob.x0) / nx
+    wy = np.tile(w, ny) * (prob.y1 - prob.y0) / ny
+    out = G.copy()
+    for d, ax, width in ((0, 1, wx), (1, 0, wy)):
+        F = np.apply_along_axis(lambda c: orc.phys_flux(prob, d, c), 2, G)
+        lam = np.apply_along_axis(lambda c: np.array([orc.wave_speed(prob, d, c)]), 2, G)[..., 0]
+        Gr, Fr, lr = np.roll(G, -1, ax), np.roll(F, -1, ax), np.roll(lam, -1, ax)
+        fr = 0.5 * (F + Fr) - 0.5 * np.maximum(lam, lr)[..., None] * (Gr - G)
+        fl = np.roll(fr, 1, ax)
+        wid = width[None, :, None] if d == 0 else width[:, None, None]
+        out -= dt / wid * (fr - fl)
+    return out.reshape(ny, n, nx, n, M).transpose(4, 0, 2, 1, 3).reshape(M, ny * nx, n * n)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_blending_alpha_one_is_subcell_fv(orc, dim):
+    xi, _ = orc.gll(3)
+    prob = orc.Problem(dim=dim, N=3, nx=5, ny=4, vol_flux=orc.VOL_KG, limiter=orc.LIM_BLEND_GIVEN)
+    u = inputs.random_smooth_euler(5, 4, xi, seed=9, dim=dim, amp=0.3)
+    dt = 0.5 * orc.compute_dt(prob, u)
+    got, _ = orc.crk_step(prob, u, dt, np.ones(prob.nelem))
+    ref = _subcell_fv(orc, prob, u, dt)
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(u))
+
+
+def _modal_state(orc, N, modes, rho=None):
+    """eps = rho p at the nodes from given orthonormal Legendre coefficients
+    m[l, k] (numpy's Legendre module, independent of the oracle)."""
+    from numpy.polynomial import legendre as L
+    xi, _ = orc.gll(N)
+    n = N + 1
+    phi = np.array([np.sqrt(2 * k + 1) * L.legval(2 * xi - 1, np.eye(n)[k]) for k in range(n)])   # [k, i]
+    eps = np.einsum("lk,ki,lj->ji", modes, phi, phi).ravel()      # index j*n + i
+    prob = orc.Problem(dim=2, N=N, nx=1, ny=1)
+    r = np.ones_like(eps) if rho is None else rho
+    u = np.zeros((4, 1, n * n))
+    u[0, 0] = r
+    u[3, 0] = (eps / r) / 0.4
+    return prob, u
+
+
+def test_indicator_features_and_special_cases(orc):
+    N = 3
+    rng = np.random.default_rng(21)
+    modes = rng.normal(size=(4, 4))
+    prob, u = _modal_state(orc, N, modes)
+    prob.alpha_max = 1.0
+    araw, a, feat = orc.indicator(prob, u)
+    assert np.max(np.abs(feat[0] - (modes ** 2).ravel() / np.sum(modes ** 2))) < 1e-13
+    # only modes of degree <= N-2 in each direction: energy 0 -> alpha 0
+    m = np.zeros((4, 4))
+    m[0, 0], m[1, 1], m[1, 0] = 3.0, 0.2, -0.1
+    prob, u = _modal_state(orc, N, m)
+    assert orc.indicator(prob, u)[0][0] == 0.0
+    # only the top mode: energy 1 -> alpha = 1 before the cap, alpha_max after it
+    m = np.zeros((4, 4))
+    m[3, 3] = 1.0
+    prob, u = _modal_state(orc, N, m)
+    prob.alpha_max = 1.0
+    assert orc.indicator(prob, u)[0][0] == 1.0
+    prob.alpha_max = 0.008
+    assert orc.indicator(prob, u)[0][0] == 0.008
+    # energy in the N-1 ring only: (c1 - c2)/c1 branch.  With m_00=1, m_{2,0}=t:
+    # E = t^2/(1+t^2); alpha = 1/(1+exp(-s/T (E - T)))
+    t = 0.05
+    m = np.zeros((4, 4))
+    m[0, 0], m[2, 0] = 1.0, t
+    prob, u = _modal_state(orc, N, m)
+    prob.alpha_max, prob.alpha_min = 1.0, 0.0
+    E = t * t / (1 + t * t)
+    T = 0.5 * 10 ** (-1.8 * 4 ** 0.25)
+    s = np.log((1 - 1e-4) / 1e-4)
+    assert abs(orc.indicator(prob, u)[0][0] - 1 / (1 + np.exp(-s / T * (E - T)))) < 1e-14
+
+
+def test_indicator_smoothing(orc):
+    xi, _ = orc.gll(3)
+    prob = orc.Problem(dim=2, N=3, nx=8, ny=8, x0=-1, x1=1, y0=-1, y1=1, limiter=1)
+    u = _khi(orc, prob)
+    araw, a, _ = orc.indicator(prob, u)
+    A = araw.reshape(8, 8)
+    nb = np.maximum.reduce([np.roll(A, 1, 0), np.roll(A, -1, 0), np.roll(A, 1, 1), np.roll(A, -1, 1)])
+    assert np.array_equal(a.reshape(8, 8), np.maximum(A, 0.5 * nb))
+    assert araw.max() == prob.alpha_max
+
+
+def test_diagnostics(orc):
+    prob = orc.Problem(dim=2, N=3, nx=3, ny=2, x1=3.0, y1=1.0)
+    u = np.zeros(prob.shape)
+    u[0], u[1], u[2], u[3] = 2.0, 1.0, 0.0, 5.0
+    d = orc.diagnostics(prob, u)
+    assert np.allclose(d["totals"], [6.0, 3.0, 0.0, 15.0], atol=1e-14)
+    p = 0.4 * (5.0 - 0.25)
+    assert abs(d["min_p"] - p) < 1e-14 and d["first_bad"] == -1
+    assert abs(d["entropy"] - 3.0 * (-2.0 * (np.log(p) - 1.4 * np.log(2.0)) / 0.4)) < 1e-13
+    u[3, 4, 7] = -1.0
+    u[1, 5, 0] = np.nan
+    d = orc.diagnostics(prob, u)
+    assert d["first_bad"] == 4 and d["nonfinite"] == 1
