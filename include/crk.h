@@ -1,0 +1,168 @@
+/*
+ * crk.h -- C ABI of the MI355X (gfx950) compact Runge-Kutta flux
+ * reconstruction (cRKFR) library with entropy-conservative (EC) and
+ * kinetic-energy-preserving (KEP) two-point volume fluxes.
+ *
+ * Method: Babbar, Chen, Ranocha, "Compact Runge-Kutta flux reconstruction
+ * methods with entropy- and/or kinetic energy-preserving fluxes",
+ * arXiv 2604.02125.  Section 2 defines the cRKFR step for
+ *   u_t + f(u)_x + B(u) g(u)_x = 0                      (eq:flux.and.non.cons)
+ * on GLL solution points with g2 correction functions: element-local inner
+ * stages (eq:crkfr.inner), time-averaged fluxes (eq:disc.avg.flux,
+ * eq:local.time.avg.non.cons), one interface numerical flux per step
+ * (eq:numflux.cons and the reduced-communication non-conservative flux
+ * B(u^n) g^avg(U)) and the final update (eq:crkfr.non.cons.final).
+ * Section 3 replaces the volume derivatives by flux differencing with a
+ * symmetric two-point flux (eq:entropy.cons.flux.dev) and a non-symmetric
+ * non-conservative term (eq:entropy.cons.noncons.dev).
+ *
+ * Conventions for every entry point:
+ *  - Return CRK_OK (0) or a negative crk_status; nothing throws.  After an
+ *    error crk_last_error() returns a message (thread-local).
+ *  - Device pointers are allocated and owned by the caller; the library
+ *    never allocates device memory and never frees caller memory.  Device
+ *    buffers must be 256-byte aligned.
+ *  - State layout (SoA, nodal): u[v][e][node], v < nvar, e = ey*nx + ex,
+ *    node = j*(N+1) + i (x index fastest); element type = double (CRK_FP64)
+ *    or float (CRK_FP32).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default
+ *    stream) and runs asynchronously; argument checks are synchronous.
+ *    Nothing reads back to the host, so the calls can be captured in a HIP
+ *    graph.  Calls that share a workspace must not run concurrently.
+ *  - dt_dev points to 2 device doubles: dt_dev[0] = time step,
+ *    dt_dev[1] = GLM cleaning speed c_h (MHD; 0 for Euler).
+ */
+#ifndef CRK_H
+#define CRK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CRK_OK = 0,
+    CRK_ERR_ARG = -1,          /* invalid argument (null, size, alias)          */
+    CRK_ERR_UNSUPPORTED = -2,  /* configuration not compiled in                 */
+    CRK_ERR_HIP = -3,          /* a HIP runtime call or kernel launch failed    */
+    CRK_ERR_STATE = -6         /* missing workspace or wrong call order         */
+} crk_status;
+
+typedef enum { CRK_EULER = 0, CRK_GLM_MHD = 1 } crk_equation;        /* nvar = dim+2, 9 */
+typedef enum {
+    CRK_VOL_CENTRAL = 0,   /* (f(u_p)+f(u_q))/2: recovers eq:flux.dev                    */
+    CRK_VOL_KG = 1,        /* Kennedy-Gruber KEP flux (Euler)                             */
+    CRK_VOL_RANOCHA = 2,   /* Ranocha EC+KEP flux (Euler)                                 */
+    CRK_VOL_DERIGS = 3     /* EC flux of Derigs et al. form + local Powell/GLM (MHD)      */
+} crk_volume_flux;
+typedef enum { CRK_FP64 = 0, CRK_FP32 = 1 } crk_precision;
+typedef enum { CRK_LIM_NONE = 0, CRK_LIM_BLEND = 1 } crk_limiter;
+
+/* Uniform Cartesian periodic mesh of nx (x ny) elements on [x0,x1] (x [y0,y1]). */
+typedef struct {
+    int dim;            /* 1 or 2                                   */
+    int nx, ny;         /* elements per direction (ny ignored in 1D) */
+    double x0, x1, y0, y1;
+    int degree;         /* N, 1 <= N <= 4                           */
+    int equation;       /* crk_equation (MHD: dim = 2)              */
+    double gamma;
+    int precision;      /* crk_precision                            */
+} crk_mesh_desc;
+
+/* Scheme: explicit RK tableau (eq:butcher), volume flux, CFL number,
+ * blending limiter.  A (stages x stages, row-major, strictly lower) and b
+ * may be NULL: then classical RK4 (N <= 3) or Butcher's six-stage
+ * fifth-order method (N = 4) is used. */
+typedef struct {
+    int stages;                /* 1..6 (ignored when A == NULL)              */
+    const double *A;           /* host pointer, copied at create             */
+    const double *b;           /* host pointer, copied at create             */
+    int volume_flux;           /* crk_volume_flux                            */
+    double cfl;                /* dt = cfl / ((N+1) max sum_d lambda_d/dx_d) */
+    int limiter;               /* crk_limiter                                */
+    double alpha_max, alpha_min;
+} crk_scheme_desc;
+
+typedef struct crk_solver crk_solver;
+typedef void *crk_stream;      /* hipStream_t */
+
+/* Create a solver for one mesh + scheme.  Host-only; copies the descriptors. */
+crk_status crk_create(const crk_mesh_desc *mesh, const crk_scheme_desc *scheme, crk_solver **out);
+crk_status crk_destroy(crk_solver *s);
+
+/* Sizes: nvar, nelem, nodes per element, bytes of one state array. */
+crk_status crk_state_layout(const crk_solver *s, int64_t *nvar, int64_t *nelem, int64_t *nnode, size_t *bytes);
+
+/* Face traces handed from the local-stage phase to the interface phase:
+ * trace[face][c][e][k] with face = 2*d + side (side 0: xi_d = 0, side 1:
+ * xi_d = 1), c < 3*nvar: U = sum_j b_j u^(j) (c < nvar), F = sum_j b_j
+ * f_d(u^(j)) (nvar <= c < 2 nvar), u^n (2 nvar <= c < 3 nvar); k = face node
+ * (j for x faces, i for y faces; 0 in 1D).  Element type = the precision. */
+crk_status crk_trace_bytes(const crk_solver *s, size_t *bytes);
+
+/* Scratch for crk_step and the reductions (traces, blending coefficients,
+ * reduction partials).  The caller allocates it once (any contents) and
+ * passes it to crk_set_workspace; it stays bound until destroy or rebind. */
+crk_status crk_workspace_bytes(const crk_solver *s, size_t *bytes);
+crk_status crk_set_workspace(crk_solver *s, void *dev, size_t bytes);
+
+/* GLL nodes xi, weights w on [0,1] and D_pq = l_q'(xi_p) (eq:diff.matrix),
+ * row-major, of degree N (host arrays of N+1, N+1, (N+1)^2 doubles; any may
+ * be NULL).  Host-only. */
+crk_status crk_reference_element(int degree, double *xi, double *w, double *D);
+
+/* dt_dev[0] = cfl / ((N+1) max_{e,p} sum_d lambda_d(u)/dx_d) with
+ * lambda_d = |v_d| + c (Euler) or max(|v_d| + c_f, c_h) (MHD), and
+ * dt_dev[1] = c_h = max_{e,p,d} (|v_d| + c_f) (MHD).  Needs the workspace. */
+crk_status crk_compute_dt(crk_solver *s, const void *u, double *dt_dev, crk_stream stream);
+
+/* Blending coefficients of the subcell-FV limiter (Hennemann-Gassner modal
+ * energy of rho*p, clipped at alpha_min, capped at alpha_max):
+ * alpha_raw[e], and alpha[e] = max(alpha_raw[e], max over face neighbours
+ * of alpha_raw/2).  Device arrays of nelem doubles; either may be NULL. */
+crk_status crk_indicator(crk_solver *s, const void *u, double *alpha_raw, double *alpha, crk_stream stream);
+
+/* Local phase (eq:crkfr.inner, eq:disc.avg.flux, Section 3 volume terms):
+ * for every element the s inner stages with flux differencing, then
+ *   u_out = u_in - dt [(1-alpha_e) V + alpha_e L]   (V = sum_j b_j R^(j);
+ * L = interior part of the first-order subcell FV update; alpha == NULL or
+ * limiter off means alpha_e = 0), plus, for MHD, the own-side
+ * non-conservative trace term, and the face traces (layout above).
+ * u_in and u_out must not alias. */
+crk_status crk_local_stages(crk_solver *s, const void *u_in, const double *dt_dev, const double *alpha,
+                            void *u_out, void *traces, crk_stream stream);
+
+/* Interface phase (eq:numflux.cons, eq:crkfr.non.cons.final): Rusanov flux
+ * of the time averages with lambda from the u^n traces of both sides,
+ * blended with the first-order flux of u^n by a = (alpha_e + alpha_nb)/2
+ * when alpha != NULL, MHD flux 1/2 B(u^n_own)(g(U^-) + g(U^+)), and the
+ * lifting with dg_R/dxi = delta_pN/w_N, dg_L/dxi = -delta_p0/w_0 applied to
+ * u_inout in place. */
+crk_status crk_interface_update(crk_solver *s, const void *traces, const double *dt_dev, const double *alpha,
+                                void *u_inout, crk_stream stream);
+
+/* One full cRKFR step u_out = step(u_in).  flags & CRK_STEP_COMPUTE_DT:
+ * compute dt_dev from u_in first (else dt_dev is an input).  With the
+ * limiter on, alpha_in (device, nelem doubles, final blending coefficients)
+ * is used if non-NULL, else the indicator runs on u_in.  Needs the
+ * workspace; u_in and u_out must not alias. */
+#define CRK_STEP_COMPUTE_DT 1
+crk_status crk_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, const double *alpha_in,
+                    int flags, crk_stream stream);
+
+/* FP64 diagnostics of u into out_dev (device, nvar + 5 doubles):
+ * totals sum_e sum_p w_p u_p |Omega_e| (nvar), total entropy
+ * sum w_p S(u_p) |Omega_e| with S = -rho (ln p - gamma ln rho)/(gamma-1),
+ * min rho, min p, count of non-finite values, first element index that is
+ * non-finite or has rho <= 0 or p <= 0 (-1 if none).  Needs the workspace. */
+crk_status crk_diagnostics(crk_solver *s, const void *u, double *out_dev, crk_stream stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char *crk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CRK_H */

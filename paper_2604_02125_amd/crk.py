@@ -1,0 +1,212 @@
+"""ctypes binding of ``libcrk.so`` (C ABI in ``include/crk.h``).
+
+Argument marshalling only: every step of the method runs in the HIP
+kernels behind the C ABI.  PyTorch provides the device memory (the state,
+the workspace, the traces) and the stream.  The library must be built
+(``__graft_entry__.build()`` or ``python -m paper_2604_02125_amd.build``);
+there is no fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcrk.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "crk.h")
+
+CRK_EULER, CRK_GLM_MHD = 0, 1
+VOL_CENTRAL, VOL_KG, VOL_RANOCHA, VOL_DERIGS = 0, 1, 2, 3
+FP64, FP32 = 0, 1
+LIM_NONE, LIM_BLEND = 0, 1
+STEP_COMPUTE_DT = 1
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("degree", C.c_int), ("equation", C.c_int), ("gamma", C.c_double), ("precision", C.c_int)]
+
+
+class SchemeDesc(C.Structure):
+    _fields_ = [("stages", C.c_int), ("A", C.POINTER(C.c_double)), ("b", C.POINTER(C.c_double)),
+                ("volume_flux", C.c_int), ("cfl", C.c_double), ("limiter", C.c_int),
+                ("alpha_max", C.c_double), ("alpha_min", C.c_double)]
+
+
+class CrkError(RuntimeError):
+    pass
+
+
+_lib = None
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+
+
+def header_functions():
+    """Names of the functions declared in include/crk.h."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"^\s*(?:crk_status|const char \*)\s*(crk_\w+)\s*\(", text, re.M)))
+
+
+def lib():
+    """Load libcrk.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CrkError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        sig = {
+            "crk_create": (st, [C.POINTER(MeshDesc), C.POINTER(SchemeDesc), C.POINTER(_vp)]),
+            "crk_destroy": (st, [_vp]),
+            "crk_state_layout": (st, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_size_t)]),
+            "crk_trace_bytes": (st, [_vp, C.POINTER(C.c_size_t)]),
+            "crk_workspace_bytes": (st, [_vp, C.POINTER(C.c_size_t)]),
+            "crk_set_workspace": (st, [_vp, _vp, C.c_size_t]),
+            "crk_reference_element": (st, [C.c_int, _dp, _dp, _dp]),
+            "crk_compute_dt": (st, [_vp, _vp, _vp, _vp]),
+            "crk_indicator": (st, [_vp, _vp, _vp, _vp, _vp]),
+            "crk_local_stages": (st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "crk_interface_update": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
+            "crk_step": (st, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp]),
+            "crk_diagnostics": (st, [_vp, _vp, _vp, _vp]),
+            "crk_last_error": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().crk_last_error().decode()
+        raise CrkError(f"{what} failed ({rc}): {msg}")
+
+
+def reference_element(degree: int):
+    """(xi, w, D) of the library's reference element (host computation)."""
+    import numpy as np
+    xi, w = np.zeros(degree + 1), np.zeros(degree + 1)
+    D = np.zeros((degree + 1, degree + 1))
+    _check(lib().crk_reference_element(degree, xi.ctypes.data_as(_dp), w.ctypes.data_as(_dp),
+                                       D.ctypes.data_as(_dp)), "crk_reference_element")
+    return xi, w, D
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One mesh + scheme.  Owns the solver handle and a device workspace."""
+
+    def __init__(self, dim=2, nx=4, ny=4, x0=0.0, x1=1.0, y0=0.0, y1=1.0, degree=3, equation=CRK_EULER,
+                 gamma=1.4, precision=FP64, A=None, b=None, volume_flux=VOL_RANOCHA, cfl=0.4,
+                 limiter=LIM_NONE, alpha_max=0.008, alpha_min=1e-3, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        m = MeshDesc(dim, nx, ny, x0, x1, y0, y1, degree, equation, gamma, precision)
+        sc = SchemeDesc()
+        if A is not None:
+            s = len(b)
+            self._A = (C.c_double * (s * s))(*[float(A[i][j]) for i in range(s) for j in range(s)])
+            self._b = (C.c_double * s)(*[float(x) for x in b])
+            sc.stages, sc.A, sc.b = s, C.cast(self._A, _dp), C.cast(self._b, _dp)
+        sc.volume_flux, sc.cfl, sc.limiter = volume_flux, cfl, limiter
+        sc.alpha_max, sc.alpha_min = alpha_max, alpha_min
+        h = _vp()
+        _check(lib().crk_create(C.byref(m), C.byref(sc), C.byref(h)), "crk_create")
+        self._h = h
+        nv, ne, nn, nb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_size_t()
+        _check(lib().crk_state_layout(h, C.byref(nv), C.byref(ne), C.byref(nn), C.byref(nb)), "crk_state_layout")
+        self.shape = (nv.value, ne.value, nn.value)
+        self.nelem = ne.value
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        tb, wb = C.c_size_t(), C.c_size_t()
+        _check(lib().crk_trace_bytes(h, C.byref(tb)), "crk_trace_bytes")
+        _check(lib().crk_workspace_bytes(h, C.byref(wb)), "crk_workspace_bytes")
+        self.trace_bytes, self.workspace_bytes = tb.value, wb.value
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        _check(lib().crk_set_workspace(h, _ptr(self.workspace), self.workspace_bytes), "crk_set_workspace")
+        self.dim, self.nx, self.ny, self.degree, self.equation = dim, nx, ny, degree, equation
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.crk_destroy(h)
+            self._h = None
+
+    # ---------------------------------------------------------------- buffers
+    def new_state(self):
+        import torch
+        return torch.empty(self.shape, dtype=self.dtype, device=self.device)
+
+    def new_traces(self):
+        import torch
+        n = self.trace_bytes // (8 if self.dtype == torch.float64 else 4)
+        return torch.empty(n, dtype=self.dtype, device=self.device)
+
+    def new_dt(self):
+        import torch
+        return torch.zeros(2, dtype=torch.float64, device=self.device)
+
+    def trace_view(self, traces):
+        """[face, c, e, k] view of a trace buffer."""
+        nf = self.degree + 1 if self.dim == 2 else 1
+        return traces.view(2 * self.dim, 3 * self.shape[0], self.nelem, nf)
+
+    def _check_state(self, u):
+        if u.dtype != self.dtype or tuple(u.shape) != self.shape or not u.is_contiguous() or u.device.type != "cuda":
+            raise CrkError(f"state must be a contiguous {self.dtype} cuda tensor of shape {self.shape}")
+
+    # ---------------------------------------------------------------- calls
+    def compute_dt(self, u, dt=None, stream=None):
+        self._check_state(u)
+        dt = self.new_dt() if dt is None else dt
+        _check(lib().crk_compute_dt(self._h, _ptr(u), _ptr(dt), _stream(stream)), "crk_compute_dt")
+        return dt
+
+    def indicator(self, u, stream=None):
+        import torch
+        self._check_state(u)
+        araw = torch.empty(self.nelem, dtype=torch.float64, device=self.device)
+        a = torch.empty_like(araw)
+        _check(lib().crk_indicator(self._h, _ptr(u), _ptr(araw), _ptr(a), _stream(stream)), "crk_indicator")
+        return araw, a
+
+    def local_stages(self, u_in, dt, u_out, traces, alpha=None, stream=None):
+        self._check_state(u_in)
+        self._check_state(u_out)
+        _check(lib().crk_local_stages(self._h, _ptr(u_in), _ptr(dt), _ptr(alpha), _ptr(u_out), _ptr(traces),
+                                      _stream(stream)), "crk_local_stages")
+
+    def interface_update(self, traces, dt, u, alpha=None, stream=None):
+        self._check_state(u)
+        _check(lib().crk_interface_update(self._h, _ptr(traces), _ptr(dt), _ptr(alpha), _ptr(u), _stream(stream)),
+               "crk_interface_update")
+
+    def step(self, u_in, u_out, dt, alpha=None, compute_dt=True, stream=None):
+        self._check_state(u_in)
+        self._check_state(u_out)
+        _check(lib().crk_step(self._h, _ptr(u_in), _ptr(u_out), _ptr(dt), _ptr(alpha),
+                              STEP_COMPUTE_DT if compute_dt else 0, _stream(stream)), "crk_step")
+
+    def diagnostics(self, u, stream=None):
+        import torch
+        self._check_state(u)
+        out = torch.empty(self.shape[0] + 5, dtype=torch.float64, device=self.device)
+        _check(lib().crk_diagnostics(self._h, _ptr(u), _ptr(out), _stream(stream)), "crk_diagnostics")
+        return out

@@ -1,0 +1,377 @@
+// crk_api.cpp -- the C ABI of include/crk.h: argument checking, reference
+// element tables, workspace layout and kernel dispatch.  No device memory is
+// allocated here; every buffer comes from the caller.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/crk.h"
+#include "crk_dispatch.hpp"
+
+using namespace crk;
+
+namespace {
+
+thread_local std::string g_err;
+
+crk_status fail(crk_status st, const char *msg)
+{
+    g_err = msg;
+    return st;
+}
+
+crk_status hip_fail(hipError_t e, const char *where)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+    g_err = buf;
+    return CRK_ERR_HIP;
+}
+
+// Legendre P_n(x) by the three-term recurrence.
+double legendre(int n, double x)
+{
+    if (n == 0) return 1.0;
+    double a = 1.0, b = x;
+    for (int k = 2; k <= n; ++k) {
+        const double c = ((2 * k - 1) * x * b - (k - 1) * a) / k;
+        a = b;
+        b = c;
+    }
+    return b;
+}
+
+// GLL nodes of degree N on [-1,1] are the roots of P_{N+1} - P_{N-1}
+// (proportional to (1 - x^2) P_N'); its derivative is (2N+1) P_N, so
+// Newton reads x <- x - (P_{N+1} - P_{N-1}) / ((2N+1) P_N).
+// Weights 2/(N(N+1) P_N^2); both mapped to [0,1].
+void gll_nodes(int N, double *xi, double *w)
+{
+    for (int k = 0; k <= N; ++k) {
+        double x = -std::cos(M_PI * k / N);
+        if (k > 0 && k < N) {
+            for (int it = 0; it < 60; ++it) {
+                const double q = legendre(N + 1, x) - legendre(N - 1, x);
+                const double dx = q / ((2 * N + 1) * legendre(N, x));
+                x -= dx;
+                if (std::fabs(dx) < 1e-17) break;
+            }
+        }
+        const double PN = legendre(N, x);
+        xi[k] = 0.5 * (x + 1.0);
+        w[k] = 1.0 / (N * (N + 1.0) * PN * PN);
+    }
+}
+
+// Differentiation matrix by barycentric weights lam_j = 1/prod_{k!=j}(xi_j - xi_k):
+// D_ij = (lam_j/lam_i)/(xi_i - xi_j) (i != j), D_ii = -sum_{j!=i} D_ij.
+void diff_matrix(int N, const double *xi, double *D)
+{
+    double lam[MAXN + 1];
+    for (int j = 0; j <= N; ++j) {
+        double p = 1.0;
+        for (int k = 0; k <= N; ++k)
+            if (k != j) p *= xi[j] - xi[k];
+        lam[j] = 1.0 / p;
+    }
+    for (int i = 0; i <= N; ++i) {
+        double s = 0.0;
+        for (int j = 0; j <= N; ++j) {
+            if (j == i) continue;
+            const double v = (lam[j] / lam[i]) / (xi[i] - xi[j]);
+            D[i * (N + 1) + j] = v;
+            s += v;
+        }
+        D[i * (N + 1) + i] = -s;
+    }
+}
+
+// Nodal -> modal map for the orthonormal Legendre basis phi_k = sqrt(2k+1) P_k(2xi-1).
+// GLL quadrature is exact for degree <= 2N-1, so the basis is discretely
+// orthogonal; only the top mode has a discrete norm gamma_N != 1.  Hence
+// V^{-1} = diag(1/gamma_k) V^T diag(w).
+void modal_inverse(int N, const double *xi, const double *w, double Vinv[MAXN + 1][MAXN + 1])
+{
+    for (int k = 0; k <= N; ++k) {
+        double g = 0.0, phi[MAXN + 1];
+        for (int i = 0; i <= N; ++i) {
+            phi[i] = std::sqrt(2.0 * k + 1.0) * legendre(k, 2.0 * xi[i] - 1.0);
+            g += w[i] * phi[i] * phi[i];
+        }
+        for (int i = 0; i <= N; ++i) Vinv[k][i] = w[i] * phi[i] / g;
+    }
+}
+
+bool is_aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+} // namespace
+
+struct crk_solver {
+    crk_mesh_desc mesh;
+    int flux, limiter, prec;
+    Tables t;
+    size_t elem_bytes;
+    size_t state_bytes, trace_bytes;
+    size_t off_partials, off_araw, off_alpha, off_traces, ws_bytes;
+    char *ws;
+};
+
+namespace {
+
+template <class F>
+hipError_t dispatch(const crk_solver *s, F &&f)
+{
+    const bool f64 = s->prec == CRK_FP64;
+    if (s->mesh.equation == CRK_GLM_MHD) return f64 ? f(Family<double, EQ_MHD, 2>()) : f(Family<float, EQ_MHD, 2>());
+    if (s->mesh.dim == 1) return f64 ? f(Family<double, EQ_EULER, 1>()) : f(Family<float, EQ_EULER, 1>());
+    return f64 ? f(Family<double, EQ_EULER, 2>()) : f(Family<float, EQ_EULER, 2>());
+}
+
+crk_status need_ws(const crk_solver *s)
+{
+    if (!s) return fail(CRK_ERR_ARG, "null solver");
+    if (!s->ws) return fail(CRK_ERR_STATE, "no workspace bound (crk_set_workspace)");
+    return CRK_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *crk_last_error(void) { return g_err.c_str(); }
+
+crk_status crk_reference_element(int N, double *xi, double *w, double *D)
+{
+    if (N < 1 || N > MAXN) return fail(CRK_ERR_UNSUPPORTED, "degree must be 1..4");
+    double x[MAXN + 1], ww[MAXN + 1], DD[(MAXN + 1) * (MAXN + 1)];
+    gll_nodes(N, x, ww);
+    diff_matrix(N, x, DD);
+    if (xi) std::memcpy(xi, x, sizeof(double) * (N + 1));
+    if (w) std::memcpy(w, ww, sizeof(double) * (N + 1));
+    if (D) std::memcpy(D, DD, sizeof(double) * (N + 1) * (N + 1));
+    return CRK_OK;
+}
+
+crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_solver **out)
+{
+    if (!m || !sc || !out) return fail(CRK_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (m->dim != 1 && m->dim != 2) return fail(CRK_ERR_ARG, "dim must be 1 or 2");
+    if (m->nx < 1 || (m->dim == 2 && m->ny < 1)) return fail(CRK_ERR_ARG, "element counts must be positive");
+    if (m->degree < 1 || m->degree > MAXN) return fail(CRK_ERR_UNSUPPORTED, "degree must be 1..4");
+    if (m->equation != CRK_EULER && m->equation != CRK_GLM_MHD) return fail(CRK_ERR_ARG, "unknown equation");
+    if (m->equation == CRK_GLM_MHD && m->dim != 2) return fail(CRK_ERR_UNSUPPORTED, "GLM-MHD is 2D only");
+    if (m->precision != CRK_FP64 && m->precision != CRK_FP32) return fail(CRK_ERR_ARG, "unknown precision");
+    if (!(m->gamma > 1.0)) return fail(CRK_ERR_ARG, "gamma must exceed 1");
+    if (!(m->x1 > m->x0) || (m->dim == 2 && !(m->y1 > m->y0))) return fail(CRK_ERR_ARG, "empty domain");
+    if (!flux_supported(m->equation == CRK_GLM_MHD ? EQ_MHD : EQ_EULER, sc->volume_flux))
+        return fail(CRK_ERR_UNSUPPORTED, "volume flux not available for this equation");
+    if (sc->limiter != CRK_LIM_NONE && sc->limiter != CRK_LIM_BLEND) return fail(CRK_ERR_ARG, "unknown limiter");
+    if (sc->limiter == CRK_LIM_BLEND && m->equation != CRK_EULER)
+        return fail(CRK_ERR_UNSUPPORTED, "the blending limiter is implemented for Euler only");
+    if (!(sc->cfl > 0.0)) return fail(CRK_ERR_ARG, "cfl must be positive");
+    const long nnode = m->dim == 2 ? (long)(m->degree + 1) * (m->degree + 1) : m->degree + 1;
+    const long nelem = m->dim == 2 ? (long)m->nx * m->ny : m->nx;
+    if (nelem * nnode >= (1L << 31)) return fail(CRK_ERR_ARG, "mesh too large");
+
+    crk_solver *s = new (std::nothrow) crk_solver();
+    if (!s) return fail(CRK_ERR_ARG, "out of host memory");
+    s->mesh = *m;
+    s->flux = sc->volume_flux;
+    s->limiter = sc->limiter;
+    s->prec = m->precision;
+    Tables &t = s->t;
+    std::memset(&t, 0, sizeof t);
+    t.dim = m->dim;
+    t.nx = m->nx;
+    t.ny = m->dim == 2 ? m->ny : 1;
+    t.N = m->degree;
+    t.M = m->equation == CRK_GLM_MHD ? 9 : m->dim + 2;
+    t.nelem = (int)nelem;
+    t.nnode = (int)nnode;
+    t.nface = m->dim == 2 ? m->degree + 1 : 1;
+    t.invdx[0] = m->nx / (m->x1 - m->x0);
+    t.invdx[1] = m->dim == 2 ? m->ny / (m->y1 - m->y0) : 0.0;
+    t.gamma = m->gamma;
+    t.cfl = sc->cfl;
+    if (sc->A && sc->b) {
+        if (sc->stages < 1 || sc->stages > MAXS) { delete s; return fail(CRK_ERR_UNSUPPORTED, "stages must be 1..6"); }
+        t.stages = sc->stages;
+        for (int i = 0; i < t.stages; ++i) {
+            t.b[i] = sc->b[i];
+            for (int j = 0; j < t.stages; ++j) {
+                const double a = sc->A[i * t.stages + j];
+                if (j >= i && a != 0.0) { delete s; return fail(CRK_ERR_ARG, "A must be strictly lower triangular"); }
+                t.A[i][j] = a;
+            }
+        }
+    } else if (m->degree <= 3) {
+        // classical RK4
+        t.stages = 4;
+        t.A[1][0] = 0.5; t.A[2][1] = 0.5; t.A[3][2] = 1.0;
+        t.b[0] = 1.0 / 6; t.b[1] = 1.0 / 3; t.b[2] = 1.0 / 3; t.b[3] = 1.0 / 6;
+    } else {
+        // Butcher's six-stage fifth-order method
+        t.stages = 6;
+        t.A[1][0] = 0.25;
+        t.A[2][0] = 0.125; t.A[2][1] = 0.125;
+        t.A[3][1] = -0.5; t.A[3][2] = 1.0;
+        t.A[4][0] = 3.0 / 16; t.A[4][3] = 9.0 / 16;
+        t.A[5][0] = -3.0 / 7; t.A[5][1] = 2.0 / 7; t.A[5][2] = 12.0 / 7; t.A[5][3] = -12.0 / 7; t.A[5][4] = 8.0 / 7;
+        t.b[0] = 7.0 / 90; t.b[2] = 32.0 / 90; t.b[3] = 12.0 / 90; t.b[4] = 32.0 / 90; t.b[5] = 7.0 / 90;
+    }
+    double xi[MAXN + 1], w[MAXN + 1], D[(MAXN + 1) * (MAXN + 1)];
+    gll_nodes(t.N, xi, w);
+    diff_matrix(t.N, xi, D);
+    for (int p = 0; p <= t.N; ++p) {
+        t.w[p] = w[p];
+        for (int q = 0; q <= t.N; ++q) t.D[p][q] = D[p * (t.N + 1) + q];
+    }
+    modal_inverse(t.N, xi, w, t.Vinv);
+    t.ind_threshold = 0.5 * std::pow(10.0, -1.8 * std::pow(t.N + 1.0, 0.25));
+    t.ind_sharpness = std::log((1.0 - 1e-4) / 1e-4);
+    t.alpha_min = sc->alpha_min;
+    t.alpha_max = sc->alpha_max;
+
+    s->elem_bytes = s->prec == CRK_FP64 ? 8 : 4;
+    s->state_bytes = (size_t)t.M * nelem * nnode * s->elem_bytes;
+    s->trace_bytes = (size_t)2 * t.dim * 3 * t.M * nelem * t.nface * s->elem_bytes;
+    size_t off = 0;
+    s->off_partials = off; off = align256(off + sizeof(double) * RED_BLOCKS * 16);
+    s->off_araw = off; off = align256(off + sizeof(double) * nelem);
+    s->off_alpha = off; off = align256(off + sizeof(double) * nelem);
+    s->off_traces = off; off = align256(off + s->trace_bytes);
+    s->ws_bytes = off;
+    s->ws = nullptr;
+    *out = s;
+    return CRK_OK;
+}
+
+crk_status crk_destroy(crk_solver *s)
+{
+    delete s;
+    return CRK_OK;
+}
+
+crk_status crk_state_layout(const crk_solver *s, int64_t *nvar, int64_t *nelem, int64_t *nnode, size_t *bytes)
+{
+    if (!s) return fail(CRK_ERR_ARG, "null solver");
+    if (nvar) *nvar = s->t.M;
+    if (nelem) *nelem = s->t.nelem;
+    if (nnode) *nnode = s->t.nnode;
+    if (bytes) *bytes = s->state_bytes;
+    return CRK_OK;
+}
+
+crk_status crk_trace_bytes(const crk_solver *s, size_t *bytes)
+{
+    if (!s || !bytes) return fail(CRK_ERR_ARG, "null argument");
+    *bytes = s->trace_bytes;
+    return CRK_OK;
+}
+
+crk_status crk_workspace_bytes(const crk_solver *s, size_t *bytes)
+{
+    if (!s || !bytes) return fail(CRK_ERR_ARG, "null argument");
+    *bytes = s->ws_bytes;
+    return CRK_OK;
+}
+
+crk_status crk_set_workspace(crk_solver *s, void *dev, size_t bytes)
+{
+    if (!s || !dev) return fail(CRK_ERR_ARG, "null argument");
+    if (!is_aligned(dev)) return fail(CRK_ERR_ARG, "workspace must be 256-byte aligned");
+    if (bytes < s->ws_bytes) return fail(CRK_ERR_ARG, "workspace too small");
+    s->ws = (char *)dev;
+    return CRK_OK;
+}
+
+crk_status crk_compute_dt(crk_solver *s, const void *u, double *dt_dev, crk_stream stream)
+{
+    crk_status st = need_ws(s);
+    if (st) return st;
+    if (!u || !dt_dev) return fail(CRK_ERR_ARG, "null pointer");
+    double *parts = (double *)(s->ws + s->off_partials);
+    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::dt(s->t, u, parts, dt_dev, (hipStream_t)stream); });
+    return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_compute_dt");
+}
+
+crk_status crk_indicator(crk_solver *s, const void *u, double *alpha_raw, double *alpha, crk_stream stream)
+{
+    if (!s || !u) return fail(CRK_ERR_ARG, "null argument");
+    if (s->mesh.equation != CRK_EULER) return fail(CRK_ERR_UNSUPPORTED, "indicator is implemented for Euler only");
+    double *araw = alpha_raw;
+    if (!araw) {
+        crk_status st = need_ws(s);
+        if (st) return st;
+        araw = (double *)(s->ws + s->off_araw);
+    }
+    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::indicator(s->t, u, araw, alpha, (hipStream_t)stream); });
+    return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_indicator");
+}
+
+crk_status crk_local_stages(crk_solver *s, const void *u_in, const double *dt_dev, const double *alpha, void *u_out,
+                            void *traces, crk_stream stream)
+{
+    if (!s || !u_in || !dt_dev || !u_out || !traces) return fail(CRK_ERR_ARG, "null argument");
+    if (u_in == u_out) return fail(CRK_ERR_ARG, "u_in and u_out must not alias");
+    if (!is_aligned(u_in) || !is_aligned(u_out) || !is_aligned(traces)) return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
+    StepPtrs p{u_in, u_out, dt_dev, s->limiter == CRK_LIM_BLEND ? alpha : nullptr, traces};
+    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::local(s->t, s->flux, p, (hipStream_t)stream); });
+    return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_local_stages");
+}
+
+crk_status crk_interface_update(crk_solver *s, const void *traces, const double *dt_dev, const double *alpha,
+                                void *u_inout, crk_stream stream)
+{
+    if (!s || !traces || !dt_dev || !u_inout) return fail(CRK_ERR_ARG, "null argument");
+    if (!is_aligned(u_inout) || !is_aligned(traces)) return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
+    StepPtrs p{nullptr, u_inout, dt_dev, s->limiter == CRK_LIM_BLEND ? alpha : nullptr, const_cast<void *>(traces)};
+    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::interface(s->t, s->flux, p, (hipStream_t)stream); });
+    return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_interface_update");
+}
+
+crk_status crk_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, const double *alpha_in, int flags,
+                    crk_stream stream)
+{
+    crk_status st = need_ws(s);
+    if (st) return st;
+    if (!u_in || !u_out || !dt_dev) return fail(CRK_ERR_ARG, "null pointer");
+    if (u_in == u_out) return fail(CRK_ERR_ARG, "u_in and u_out must not alias");
+    if (flags & CRK_STEP_COMPUTE_DT) {
+        st = crk_compute_dt(s, u_in, dt_dev, stream);
+        if (st) return st;
+    }
+    const double *alpha = nullptr;
+    if (s->limiter == CRK_LIM_BLEND) {
+        if (alpha_in) {
+            alpha = alpha_in;
+        } else {
+            double *a = (double *)(s->ws + s->off_alpha);
+            st = crk_indicator(s, u_in, (double *)(s->ws + s->off_araw), a, stream);
+            if (st) return st;
+            alpha = a;
+        }
+    }
+    void *tr = s->ws + s->off_traces;
+    st = crk_local_stages(s, u_in, dt_dev, alpha, u_out, tr, stream);
+    if (st) return st;
+    return crk_interface_update(s, tr, dt_dev, alpha, u_out, stream);
+}
+
+crk_status crk_diagnostics(crk_solver *s, const void *u, double *out_dev, crk_stream stream)
+{
+    crk_status st = need_ws(s);
+    if (st) return st;
+    if (!u || !out_dev) return fail(CRK_ERR_ARG, "null pointer");
+    double *parts = (double *)(s->ws + s->off_partials);
+    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::diag(s->t, u, parts, out_dev, (hipStream_t)stream); });
+    return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_diagnostics");
+}
+
+} // extern "C"

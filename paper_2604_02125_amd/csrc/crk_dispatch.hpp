@@ -1,0 +1,25 @@
+// crk_dispatch.hpp -- runtime (degree, volume flux) -> template instance.
+// One "family" per (precision, equation, dimension) is compiled in its own
+// translation unit (crk_family_*.hip) so that the instances build in parallel.
+#pragma once
+#include "crk_kernels.hpp"
+
+namespace crk {
+
+template <typename real, int EQ, int DIM>
+struct Family {
+    static hipError_t local(const Tables &t, int flux, const StepPtrs &p, hipStream_t s);
+    static hipError_t interface(const Tables &t, int flux, const StepPtrs &p, hipStream_t s);
+    static hipError_t indicator(const Tables &t, const void *u, double *araw, double *alpha, hipStream_t s);
+    static hipError_t dt(const Tables &t, const void *u, double *partials, double *dt, hipStream_t s);
+    static hipError_t diag(const Tables &t, const void *u, double *partials, double *out, hipStream_t s);
+};
+
+// fluxes compiled for an equation system
+constexpr bool flux_supported(int eq, int flux)
+{
+    return eq == EQ_EULER ? (flux == VOL_CENTRAL || flux == VOL_KG || flux == VOL_RANOCHA)
+                          : (flux == VOL_CENTRAL || flux == VOL_DERIGS);
+}
+
+} // namespace crk

@@ -1,0 +1,696 @@
+// crk_kernels.hpp -- HIP kernels of one cRKFR step on gfx950.
+//
+// Mapping: one lane per solution node, the (N+1)^d nodes of an element in
+// consecutive lanes, floor(256/(N+1)^d) elements per 256-lane workgroup.
+// A stage stages its per-node fields (primitives, logarithms) in LDS so that
+// every lane can form the two-point fluxes with the nodes on its x- and
+// y-lines; the stage states, stage residuals and time averages stay in
+// registers.  State and trace arrays are SoA with the node (or face-node)
+// index fastest, so a wavefront touches contiguous memory.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "crk_physics.hpp"
+
+namespace crk {
+
+constexpr int MAXN = 4;      // highest compiled degree
+constexpr int MAXS = 6;      // highest stage count
+constexpr int BLOCK = 256;   // lanes per workgroup of the element kernels
+constexpr int RED_BLOCKS = 1024;  // max workgroups of the reduction kernels
+
+// Everything a kernel needs besides its pointers; passed by value.
+struct Tables {
+    int dim, nx, ny, N, M, nelem, nnode, nface;  // nface = nodes per face
+    double invdx[2];
+    double gamma;
+    int stages;
+    double A[MAXS][MAXS];
+    double b[MAXS];
+    double D[MAXN + 1][MAXN + 1];     // D_pq = l_q'(xi_p) on [0,1]
+    double w[MAXN + 1];               // GLL weights on [0,1]
+    double Vinv[MAXN + 1][MAXN + 1];  // nodal -> orthonormal Legendre modal
+    double cfl;
+    double ind_threshold, ind_sharpness, alpha_min, alpha_max;
+};
+
+struct StepPtrs {
+    const void *u_in;
+    void *u_out;
+    const double *dt;      // [dt, c_h]
+    const double *alpha;   // final blending coefficients or nullptr
+    void *traces;
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ long neighbour(const Tables &t, long e, int d, int side)
+{
+    if (t.dim == 1) return side ? (e + 1 == t.nx ? 0 : e + 1) : (e == 0 ? t.nx - 1 : e - 1);
+    long ex = e % t.nx, ey = e / t.nx;
+    if (d == 0) ex = side ? (ex + 1 == t.nx ? 0 : ex + 1) : (ex == 0 ? t.nx - 1 : ex - 1);
+    else ey = side ? (ey + 1 == t.ny ? 0 : ey + 1) : (ey == 0 ? t.ny - 1 : ey - 1);
+    return ey * t.nx + ex;
+}
+
+template <typename real, int EQ, int DIM, int FLUX> struct PhysOf;
+template <typename real, int DIM, int FLUX> struct PhysOf<real, EQ_EULER, DIM, FLUX> { using type = EulerP<real, DIM, FLUX>; };
+template <typename real, int DIM, int FLUX> struct PhysOf<real, EQ_MHD, DIM, FLUX> { using type = MhdP<real, FLUX>; };
+
+template <typename real>
+__device__ __forceinline__ Ctx<real> make_ctx(const Tables &t, const double *dt)
+{
+    Ctx<real> c;
+    c.gamma = real(t.gamma);
+    c.gm1 = real(t.gamma - 1.0);
+    c.inv_gm1 = real(1.0 / (t.gamma - 1.0));
+    c.ch = dt ? real(dt[1]) : real(0);
+    return c;
+}
+
+// ---------------------------------------------------------------- K2: local stages
+// For every element: s inner stages u^(i) = u^n - dt sum_{j<i} a_ij R^(j)
+// with R^(i)_p = sum_d 1/dx_d sum_q [2 D_pq f_S,d(u_p,u_q) + D_pq B_d(u_p) g_d(u_q)]
+// (eq:crkfr.inner with the volume terms of Section 3); V = sum_j b_j R^(j);
+// face traces U, F; provisional update u* (see crk_local_stages).
+template <typename real, int EQ, int DIM, int N, int FLUX>
+__global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs a)
+{
+    using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
+    constexpr int n1 = N + 1;
+    constexpr int NP = DIM == 2 ? n1 * n1 : n1;
+    constexpr int EPB = BLOCK / NP;
+    constexpr int M = Phys::M;
+    constexpr int NF = Phys::NF;
+    __shared__ real lds[NF][BLOCK];
+
+    const int tid = threadIdx.x;
+    int le = tid / NP;
+    const int node = tid - le * NP;
+    const long e = (long)blockIdx.x * EPB + le;
+    const bool valid = (le < EPB) && (e < t.nelem);
+    if (le >= EPB) le = 0;                 // spare lanes read element 0's fields
+    const long es = valid ? e : 0;
+    const int base = le * NP;
+    const int pd[2] = {node % n1, DIM == 2 ? node / n1 : 0};
+    const long E = t.nelem;
+
+    const Ctx<real> ctx = make_ctx<real>(t, a.dt);
+    const double dt = a.dt[0];
+    const real rdt = real(dt);
+
+    // per-lane coefficients: for rotation k = 1..N the neighbour q = (p_d + k) mod (N+1)
+    real Dk[DIM][N > 0 ? N : 1], Ddiag[DIM], invw[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+        for (int k = 1; k <= N; ++k) {
+            real c = real(0);
+#pragma unroll
+            for (int r = 0; r < n1; ++r)
+                if (pd[d] == r) c = real(2.0 * t.D[r][(r + k) % n1] * t.invdx[d]);
+            Dk[d][k - 1] = c;
+        }
+        real dg = real(0), iw = real(0);
+#pragma unroll
+        for (int r = 0; r < n1; ++r)
+            if (pd[d] == r) { dg = real(2.0 * t.D[r][r] * t.invdx[d]); iw = real(t.invdx[d] / t.w[r]); }
+        Ddiag[d] = dg;
+        invw[d] = iw;
+    }
+    // MHD: plain D_pq / dx_d for the non-conservative term, all q
+    real Dn[DIM][n1];
+    if constexpr (EQ == EQ_MHD) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+            for (int q = 0; q < n1; ++q) {
+                real c = real(0);
+#pragma unroll
+                for (int r = 0; r < n1; ++r)
+                    if (pd[d] == r) c = real(t.D[r][q] * t.invdx[d]);
+                Dn[d][q] = c;
+            }
+    }
+
+    const real *uin = (const real *)a.u_in;
+    real un[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) un[v] = uin[((long)v * E + es) * NP + node];
+
+    const real alpha = (a.alpha != nullptr && valid) ? real(a.alpha[es]) : real(0);
+    const bool blend = a.alpha != nullptr;
+
+    // face membership of this node
+    bool onface[DIM];
+    int side[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        onface[d] = (pd[d] == 0) || (pd[d] == N);
+        side[d] = (pd[d] == N) ? 1 : 0;
+    }
+
+    real Z[MAXS][M];     // Z[k] = sum_{j<k} a_kj R^(j), for the stages still to come
+#pragma unroll
+    for (int k = 0; k < MAXS; ++k)
+#pragma unroll
+        for (int v = 0; v < M; ++v) Z[k][v] = real(0);
+    real V[M], U[M], F[DIM][M], Fnc[DIM][M], Lint[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+        V[v] = real(0); U[v] = real(0); Lint[v] = real(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) { F[d][v] = real(0); Fnc[d][v] = real(0); }
+    }
+
+    for (int i = 0; i < t.stages; ++i) {
+        // stage state
+        real us[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            real z = real(0);
+#pragma unroll
+            for (int k = 0; k < MAXS; ++k)
+                if (k == i) z = Z[k][v];
+            us[v] = un[v] - rdt * z;
+        }
+        real nd[NF];
+        Phys::node(us, nd, ctx);
+        if (i > 0) __syncthreads();       // previous stage finished reading LDS
+#pragma unroll
+        for (int f = 0; f < NF; ++f) lds[f][tid] = nd[f];
+        __syncthreads();
+
+        real R[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) R[v] = real(0);
+        const real bi = real(t.b[i]);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            // off-diagonal pairs along the d-line
+#pragma unroll
+            for (int k = 1; k <= N; ++k) {
+                int qd = pd[d] + k;
+                if (qd >= n1) qd -= n1;
+                const int q = (DIM == 1) ? qd : (d == 0 ? pd[1] * n1 + qd : qd * n1 + pd[0]);
+                real ndq[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) ndq[f] = lds[f][base + q];
+                real fs[M];
+                Phys::pair(d, nd, ndq, fs, ctx);
+#pragma unroll
+                for (int v = 0; v < M; ++v) R[v] += Dk[d][k - 1] * fs[v];
+            }
+            // diagonal term 2 D_pp f_d(u_p) (non-zero only at the two ends of
+            // the line) and the face traces in the same branch
+            if (onface[d]) {
+                real fp[M];
+                Phys::phys(d, nd, fp, ctx);
+#pragma unroll
+                for (int v = 0; v < M; ++v) {
+                    R[v] += Ddiag[d] * fp[v];
+                    F[d][v] += bi * fp[v];
+                }
+                if constexpr (EQ == EQ_MHD) {
+                    real o[M];
+                    MhdP<real, FLUX>::btimes(d, nd, nd[5 + d], nd[8], o);
+#pragma unroll
+                    for (int v = 0; v < M; ++v) Fnc[d][v] += bi * o[v];
+                }
+            }
+            if constexpr (EQ == EQ_MHD) {
+                // sum_q D_pq B_d(u_p) g_d(u_q) = B_d(u_p) (sum_q D_pq g_d(u_q))
+                real gB = real(0), gpsi = real(0);
+#pragma unroll
+                for (int q = 0; q < n1; ++q) {
+                    const int qq = (d == 0 ? pd[1] * n1 + q : q * n1 + pd[0]);
+                    gB += Dn[d][q] * lds[5 + d][base + qq];
+                    gpsi += Dn[d][q] * lds[8][base + qq];
+                }
+                real o[M];
+                MhdP<real, FLUX>::btimes(d, nd, gB, gpsi, o);
+#pragma unroll
+                for (int v = 0; v < M; ++v) R[v] += o[v];
+            }
+            // first-order subcell fluxes of the blending limiter, from u^n = u^(1)
+            if (i == 0 && blend && alpha > real(0)) {
+                real fr[M], fl[M];
+#pragma unroll
+                for (int v = 0; v < M; ++v) { fr[v] = real(0); fl[v] = real(0); }
+                real fp[M];
+                Phys::phys(d, nd, fp, ctx);
+                const real *up = un;
+                const real lp = Phys::speed(d, nd, ctx);
+#pragma unroll
+                for (int sgn = 0; sgn < 2; ++sgn) {
+                    const int qd = sgn ? pd[d] + 1 : pd[d] - 1;
+                    if (qd < 0 || qd > N) continue;
+                    const int q = (DIM == 1) ? qd : (d == 0 ? pd[1] * n1 + qd : qd * n1 + pd[0]);
+                    real ndq[NF], fq[M], uq[M];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) ndq[f] = lds[f][base + q];
+                    Phys::phys(d, ndq, fq, ctx);
+                    Phys::cons(ndq, uq, ctx);
+                    const real lam = dmax(lp, Phys::speed(d, ndq, ctx));
+#pragma unroll
+                    for (int v = 0; v < M; ++v) {
+                        if (sgn) fr[v] = real(0.5) * (fp[v] + fq[v]) - real(0.5) * lam * (uq[v] - up[v]);
+                        else fl[v] = real(0.5) * (fq[v] + fp[v]) - real(0.5) * lam * (up[v] - uq[v]);
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < M; ++v) Lint[v] += invw[d] * (fr[v] - fl[v]);
+            }
+        }
+        // stage bookkeeping
+#pragma unroll
+        for (int k = 0; k < MAXS; ++k) {
+            if (k > i && k < t.stages) {
+                const real aki = real(t.A[k][i]);
+#pragma unroll
+                for (int v = 0; v < M; ++v) Z[k][v] += aki * R[v];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            V[v] += bi * R[v];
+            U[v] += bi * us[v];
+        }
+    }
+
+    if (!valid) return;
+    real *uout = (real *)a.u_out;
+    real res[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) res[v] = un[v] - rdt * ((real(1) - alpha) * V[v] + alpha * Lint[v]);
+    if constexpr (EQ == EQ_MHD) {
+        // own-side non-conservative trace term of the lifting
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            if (onface[d]) {
+                const real sg = side[d] ? rdt * invw[d] : -rdt * invw[d];
+#pragma unroll
+                for (int v = 0; v < M; ++v) res[v] += sg * Fnc[d][v];
+            }
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) uout[((long)v * E + e) * NP + node] = res[v];
+
+    // traces
+    real *tr = (real *)a.traces;
+    const int nf = DIM == 2 ? n1 : 1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        if (!onface[d]) continue;
+        const int face = 2 * d + side[d];
+        const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
+        real *tb = tr + ((long)face * 3 * M * E + e) * nf + kk;
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            tb[((long)v * E) * nf] = U[v];
+            tb[((long)(M + v) * E) * nf] = F[d][v];
+            tb[((long)(2 * M + v) * E) * nf] = un[v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- K3: interface + final update
+template <typename real, int EQ, int DIM, int N, int FLUX>
+__global__ void __launch_bounds__(BLOCK) k_interface(const Tables t, const StepPtrs a)
+{
+    using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
+    constexpr int n1 = N + 1;
+    constexpr int NP = DIM == 2 ? n1 * n1 : n1;
+    constexpr int EPB = BLOCK / NP;
+    constexpr int M = Phys::M;
+    constexpr int NF = Phys::NF;
+    const int tid = threadIdx.x;
+    const int le = tid / NP;
+    const int node = tid - le * NP;
+    const long e = (long)blockIdx.x * EPB + le;
+    if (le >= EPB || e >= t.nelem) return;
+    const int pd[2] = {node % n1, DIM == 2 ? node / n1 : 0};
+    bool any = false;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) any |= (pd[d] == 0 || pd[d] == N);
+    if (!any) return;
+
+    const long E = t.nelem;
+    const int nf = DIM == 2 ? n1 : 1;
+    const Ctx<real> ctx = make_ctx<real>(t, a.dt);
+    const real rdt = real(a.dt[0]);
+    const bool blend = a.alpha != nullptr;
+    const real alpha_e = blend ? real(a.alpha[e]) : real(0);
+    const real *tr = (const real *)a.traces;
+    real *uo = (real *)a.u_out;
+
+    real u[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) u[v] = uo[((long)v * E + e) * NP + node];
+
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        if (!(pd[d] == 0 || pd[d] == N)) continue;
+        const int side = pd[d] == N ? 1 : 0;
+        const long en = neighbour(t, e, d, side);
+        const int face = 2 * d + side, nface = 2 * d + 1 - side;
+        const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
+        const real *to = tr + ((long)face * 3 * M * E + e) * nf + kk;
+        const real *tn = tr + ((long)nface * 3 * M * E + en) * nf + kk;
+        real Uo[M], Fo[M], uno[M], Un[M], Fn[M], unn[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            Uo[v] = to[((long)v * E) * nf];
+            Fo[v] = to[((long)(M + v) * E) * nf];
+            uno[v] = to[((long)(2 * M + v) * E) * nf];
+            Un[v] = tn[((long)v * E) * nf];
+            Fn[v] = tn[((long)(M + v) * E) * nf];
+            unn[v] = tn[((long)(2 * M + v) * E) * nf];
+        }
+        real ndo[NF], ndn[NF];
+        Phys::node_basic(uno, ndo, ctx);
+        Phys::node_basic(unn, ndn, ctx);
+        const real lam = dmax(Phys::speed(d, ndo, ctx), Phys::speed(d, ndn, ctx));
+        // left (-) / right (+) of the interface
+        const real *UL = side ? Uo : Un, *UR = side ? Un : Uo;
+        const real *FL = side ? Fo : Fn, *FR = side ? Fn : Fo;
+        real Fs[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) Fs[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * lam * (UR[v] - UL[v]);
+        if (blend) {
+            const real aface = real(0.5) * (alpha_e + real(a.alpha[en]));
+            if (aface > real(0)) {
+                real fo[M], fn[M];
+                Phys::phys(d, ndo, fo, ctx);
+                Phys::phys(d, ndn, fn, ctx);
+                const real *fL = side ? fo : fn, *fR = side ? fn : fo;
+                const real *uL = side ? uno : unn, *uR = side ? unn : uno;
+#pragma unroll
+                for (int v = 0; v < M; ++v) {
+                    const real flo = real(0.5) * (fL[v] + fR[v]) - real(0.5) * lam * (uR[v] - uL[v]);
+                    Fs[v] = (real(1) - aface) * Fs[v] + aface * flo;
+                }
+            }
+        }
+        real jump[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) jump[v] = Fs[v] - (real(1) - alpha_e) * Fo[v];
+        if constexpr (EQ == EQ_MHD) {
+            real o[M];
+            MhdP<real, FLUX>::btimes(d, ndo, real(0.5) * (UL[5 + d] + UR[5 + d]), real(0.5) * (UL[8] + UR[8]), o);
+#pragma unroll
+            for (int v = 0; v < M; ++v) jump[v] += o[v];
+        }
+        const real coef = rdt * real(t.invdx[d] / t.w[0]);
+#pragma unroll
+        for (int v = 0; v < M; ++v) u[v] += side ? -coef * jump[v] : coef * jump[v];
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) uo[((long)v * E + e) * NP + node] = u[v];
+}
+
+// ---------------------------------------------------------------- K1: time step
+// Per node sum_d lambda_d/dx_d (Euler) or max_d (|v_d| + c_f) (MHD); block
+// maxima into partials, then one block finishes.  Deterministic, no atomics.
+template <typename real, int EQ, int DIM>
+__global__ void __launch_bounds__(BLOCK) k_dt_partial(const Tables t, const void *u_, double *partials)
+{
+    using Phys = typename PhysOf<real, EQ, DIM, (EQ == EQ_MHD ? VOL_DERIGS : VOL_KG)>::type;
+    constexpr int M = Phys::M;
+    __shared__ double red[BLOCK];
+    const real *u = (const real *)u_;
+    const long total = (long)t.nelem * t.nnode;
+    Ctx<real> ctx = make_ctx<real>(t, nullptr);
+    double mx = 0.0;
+    for (long idx = (long)blockIdx.x * BLOCK + threadIdx.x; idx < total; idx += (long)gridDim.x * BLOCK) {
+        real us[M], nd[Phys::NF];
+#pragma unroll
+        for (int v = 0; v < M; ++v) us[v] = u[(long)v * total + idx];
+        Phys::node_basic(us, nd, ctx);
+        double s = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            if constexpr (EQ == EQ_MHD) s = fmax(s, (double)MhdP<real, VOL_DERIGS>::fast(d, nd, ctx));
+            else s += (double)Phys::speed(d, nd, ctx) * t.invdx[d];
+        }
+        mx = fmax(mx, s);
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+static __global__ void __launch_bounds__(BLOCK) k_dt_final(const Tables t, const double *partials, int nparts, int is_mhd, double *dt)
+{
+    __shared__ double red[BLOCK];
+    double mx = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += BLOCK) mx = fmax(mx, partials[k]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = red[0];
+        if (is_mhd) {
+            // every lambda_d = max(|v_d| + c_f, c_h) equals c_h = the global max
+            double sdx = 0.0;
+            for (int d = 0; d < t.dim; ++d) sdx += t.invdx[d];
+            dt[0] = t.cfl / ((t.N + 1) * m * sdx);
+            dt[1] = m;
+        } else {
+            dt[0] = t.cfl / ((t.N + 1) * m);
+            dt[1] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- K8: modal indicator
+template <typename real, int DIM, int N>
+__global__ void __launch_bounds__(BLOCK) k_indicator(const Tables t, const void *u_, double *alpha_raw)
+{
+    constexpr int n1 = N + 1;
+    constexpr int NP = DIM == 2 ? n1 * n1 : n1;
+    constexpr int EPB = BLOCK / NP;
+    __shared__ double eps[BLOCK];
+    __shared__ double en[3][BLOCK];
+    const int tid = threadIdx.x;
+    int le = tid / NP;
+    const int node = tid - le * NP;
+    const long e = (long)blockIdx.x * EPB + le;
+    const bool valid = (le < EPB) && (e < t.nelem);
+    if (le >= EPB) le = 0;
+    const long es = valid ? e : 0;
+    const long E = t.nelem;
+    const real *u = (const real *)u_;
+    constexpr int M = DIM + 2;
+    double us[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) us[v] = (double)u[((long)v * E + es) * NP + node];
+    double ke = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) ke += us[1 + k] * us[1 + k];
+    const double p = (t.gamma - 1.0) * (us[DIM + 1] - 0.5 * ke / us[0]);
+    eps[tid] = us[0] * p;
+    __syncthreads();
+    // modal coefficient m_kl of this lane's mode (k, l) = (i, j)
+    const int mk = node % n1, ml = DIM == 2 ? node / n1 : 0;
+    double rk[n1], rl[n1];
+#pragma unroll
+    for (int c = 0; c < n1; ++c) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int r = 0; r < n1; ++r) {
+            if (mk == r) a = t.Vinv[r][c];
+            if (ml == r) b = t.Vinv[r][c];
+        }
+        rk[c] = a;
+        rl[c] = b;
+    }
+    double m = 0.0;
+    if (DIM == 1) {
+#pragma unroll
+        for (int i = 0; i < n1; ++i) m += rk[i] * eps[le * NP + i];
+    } else {
+#pragma unroll
+        for (int j = 0; j < n1; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < n1; ++i) s += rk[i] * eps[le * NP + j * n1 + i];
+            m += rl[j] * s;
+        }
+    }
+    const double e2 = m * m;
+    en[0][tid] = e2;
+    en[1][tid] = (mk <= N - 1 && ml <= N - 1) ? e2 : 0.0;
+    en[2][tid] = (mk <= N - 2 && ml <= N - 2) ? e2 : 0.0;
+    __syncthreads();
+    if (!valid || node != 0) return;
+    double tot = 0.0, c1 = 0.0, c2 = 0.0;
+    for (int p = 0; p < NP; ++p) {
+        tot += en[0][le * NP + p];
+        c1 += en[1][le * NP + p];
+        c2 += en[2][le * NP + p];
+    }
+    const double E1 = (tot - c1) / tot, E2 = (c1 - c2) / c1;
+    const double En = E1 > E2 ? E1 : E2;
+    double al = 1.0 / (1.0 + exp(-(t.ind_sharpness / t.ind_threshold) * (En - t.ind_threshold)));
+    if (al < t.alpha_min) al = 0.0;
+    if (al > 1.0 - t.alpha_min) al = 1.0;
+    if (al > t.alpha_max) al = t.alpha_max;
+    alpha_raw[e] = al;
+}
+
+static __global__ void __launch_bounds__(BLOCK) k_smooth(const Tables t, const double *alpha_raw, double *alpha)
+{
+    const long e = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= t.nelem) return;
+    double a = alpha_raw[e];
+    for (int d = 0; d < t.dim; ++d)
+        for (int s = 0; s < 2; ++s) a = fmax(a, 0.5 * alpha_raw[neighbour(t, e, d, s)]);
+    alpha[e] = a;
+}
+
+// ---------------------------------------------------------------- K5: diagnostics
+// partial layout per block: [M totals, entropy, min rho, min p, nonfinite, first bad]
+template <typename real, int EQ, int DIM>
+__global__ void __launch_bounds__(BLOCK) k_diag_partial(const Tables t, const void *u_, double *partials)
+{
+    constexpr int M = EQ == EQ_MHD ? 9 : DIM + 2;
+    constexpr int K = M + 5;
+    __shared__ double red[K][BLOCK];
+    const real *u = (const real *)u_;
+    const long total = (long)t.nelem * t.nnode;
+    const int n1 = t.N + 1;
+    double acc[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc[c] = 0.0;
+    acc[M + 1] = INFINITY; acc[M + 2] = INFINITY; acc[M + 4] = INFINITY;
+    const double vol = (DIM == 2) ? 1.0 / (t.invdx[0] * t.invdx[1]) : 1.0 / t.invdx[0];
+    for (long idx = (long)blockIdx.x * BLOCK + threadIdx.x; idx < total; idx += (long)gridDim.x * BLOCK) {
+        const long e = idx / t.nnode;
+        const int node = (int)(idx - e * t.nnode);
+        const int i = node % n1, j = node / n1;
+        double wq = t.w[i] * (DIM == 2 ? t.w[j] : 1.0) * vol;
+        double us[M];
+        bool bad = false;
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+            us[v] = (double)u[(long)v * total + idx];
+            if (!isfinite(us[v])) { acc[M + 3] += 1.0; bad = true; }
+            acc[v] += wq * us[v];
+        }
+        double rho = us[0], p;
+        if constexpr (EQ == EQ_MHD) {
+            const double vv = (us[1] * us[1] + us[2] * us[2] + us[3] * us[3]) / rho;
+            const double BB = us[5] * us[5] + us[6] * us[6] + us[7] * us[7];
+            p = (t.gamma - 1.0) * (us[4] - 0.5 * vv - 0.5 * BB - 0.5 * us[8] * us[8]);
+        } else {
+            double ke = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) ke += us[1 + k] * us[1 + k];
+            p = (t.gamma - 1.0) * (us[DIM + 1] - 0.5 * ke / rho);
+        }
+        if (!(rho > 0.0) || !(p > 0.0)) bad = true;
+        acc[M + 1] = fmin(acc[M + 1], rho);
+        acc[M + 2] = fmin(acc[M + 2], p);
+        if (rho > 0.0 && p > 0.0) acc[M] += wq * (-rho * (log(p) - t.gamma * log(rho)) / (t.gamma - 1.0));
+        if (bad) acc[M + 4] = fmin(acc[M + 4], (double)e);
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const double x = red[c][threadIdx.x], y = red[c][threadIdx.x + w];
+                red[c][threadIdx.x] = (c == M + 1 || c == M + 2 || c == M + 4) ? fmin(x, y) : x + y;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) partials[(long)blockIdx.x * K + c] = red[c][0];
+    }
+}
+
+static __global__ void k_diag_final(int M, const double *partials, int nparts, double *out)
+{
+    // one lane per quantity, serial over blocks in index order (deterministic)
+    const int c = threadIdx.x;
+    const int K = M + 5;
+    if (c >= K) return;
+    const bool ismin = (c == M + 1 || c == M + 2 || c == M + 4);
+    double acc = ismin ? INFINITY : 0.0;
+    for (int k = 0; k < nparts; ++k) {
+        const double x = partials[(long)k * K + c];
+        acc = ismin ? fmin(acc, x) : acc + x;
+    }
+    if (c == M + 4) acc = isinf(acc) ? -1.0 : acc;
+    out[c] = acc;
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename real, int EQ, int DIM, int N, int FLUX>
+hipError_t launch_local(const Tables &t, const StepPtrs &p, hipStream_t s)
+{
+    constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
+    constexpr int EPB = BLOCK / NP;
+    const int grid = (t.nelem + EPB - 1) / EPB;
+    hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(BLOCK), 0, s, t, p);
+    return hipGetLastError();
+}
+
+template <typename real, int EQ, int DIM, int N, int FLUX>
+hipError_t launch_interface(const Tables &t, const StepPtrs &p, hipStream_t s)
+{
+    constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
+    constexpr int EPB = BLOCK / NP;
+    const int grid = (t.nelem + EPB - 1) / EPB;
+    hipLaunchKernelGGL((k_interface<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(BLOCK), 0, s, t, p);
+    return hipGetLastError();
+}
+
+template <typename real, int DIM, int N>
+hipError_t launch_indicator(const Tables &t, const void *u, double *araw, double *alpha, hipStream_t s)
+{
+    constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
+    constexpr int EPB = BLOCK / NP;
+    const int grid = (t.nelem + EPB - 1) / EPB;
+    hipLaunchKernelGGL((k_indicator<real, DIM, N>), dim3(grid), dim3(BLOCK), 0, s, t, u, araw);
+    if (alpha)
+        hipLaunchKernelGGL(k_smooth, dim3((t.nelem + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, t, (const double *)araw, alpha);
+    return hipGetLastError();
+}
+
+inline int reduction_blocks(const Tables &t)
+{
+    const long total = (long)t.nelem * t.nnode;
+    long g = (total + BLOCK - 1) / BLOCK;
+    return (int)(g < RED_BLOCKS ? g : RED_BLOCKS);
+}
+
+template <typename real, int EQ, int DIM>
+hipError_t launch_dt(const Tables &t, const void *u, double *partials, double *dt, hipStream_t s)
+{
+    const int g = reduction_blocks(t);
+    hipLaunchKernelGGL((k_dt_partial<real, EQ, DIM>), dim3(g), dim3(BLOCK), 0, s, t, u, partials);
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(BLOCK), 0, s, t, (const double *)partials, g, EQ == EQ_MHD ? 1 : 0, dt);
+    return hipGetLastError();
+}
+
+template <typename real, int EQ, int DIM>
+hipError_t launch_diag(const Tables &t, const void *u, double *partials, double *out, hipStream_t s)
+{
+    const int g = reduction_blocks(t);
+    hipLaunchKernelGGL((k_diag_partial<real, EQ, DIM>), dim3(g), dim3(BLOCK), 0, s, t, u, partials);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, t.M, (const double *)partials, g, out);
+    return hipGetLastError();
+}
+
+} // namespace crk

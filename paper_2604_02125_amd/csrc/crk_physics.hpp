@@ -1,0 +1,313 @@
+// crk_physics.hpp -- device-side physics and two-point fluxes of the cRKFR
+// library (gfx950).  Each physics policy describes, for one equation system
+// and one volume flux:
+//   - M: number of conserved variables;
+//   - NF: number of per-node fields staged in LDS for the two-point fluxes
+//     (primitive variables plus whatever a flux needs per node, such as the
+//     logarithms used by the logarithmic means);
+//   - node():  fields from the conserved state;
+//   - pair():  symmetric two-point flux f_S,d(u_a, u_b)  (eq:entropy.cons.flux.dev);
+//   - phys():  physical flux f_d(u);
+//   - speed(): largest |eigenvalue| of f'+Bg' in direction d (eq:combined.wave.speed);
+//   - cons():  conserved state from the fields (for the subcell fluxes).
+// Systems: compressible Euler (eq:flux.and.non.cons with B = 0) and ideal
+// GLM-MHD with the Powell / GLM non-conservative products.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace crk {
+
+enum { VOL_CENTRAL = 0, VOL_KG = 1, VOL_RANOCHA = 2, VOL_DERIGS = 3 };
+enum { EQ_EULER = 0, EQ_MHD = 1 };
+
+template <typename real>
+struct Ctx {
+    real gamma, gm1, inv_gm1, ch;
+};
+
+template <typename real> __device__ __forceinline__ real dsqrt(real x) { return sqrt(x); }
+template <> __device__ __forceinline__ float dsqrt<float>(float x) { return sqrtf(x); }
+template <typename real> __device__ __forceinline__ real dlog(real x) { return log(x); }
+template <> __device__ __forceinline__ float dlog<float>(float x) { return logf(x); }
+template <typename real> __device__ __forceinline__ real dabs(real x) { return fabs(x); }
+template <> __device__ __forceinline__ float dabs<float>(float x) { return fabsf(x); }
+template <typename real> __device__ __forceinline__ real dmax(real a, real b) { return a > b ? a : b; }
+
+// Switch point of the logarithmic mean between its series and log forms, in
+// u = ((x - y)/(x + y))^2: the series truncated after u^3 is accurate to the
+// working precision below it, and ln y - ln x loses no more than a few ulps
+// of relative accuracy above it.
+template <typename real> struct LnMeanSwitch;
+template <> struct LnMeanSwitch<double> { static constexpr double value = 1e-4; };
+template <> struct LnMeanSwitch<float> { static constexpr float value = 1e-2f; };
+
+// Logarithmic mean (x - y)/(ln x - ln y) from precomputed logarithms, and its
+// reciprocal.  With f = (x - y)/(x + y), u = f^2: ln(x/y) = 2 artanh f =
+// 2 f (1 + u/3 + u^2/5 + u^3/7 + ...), so near x = y the mean is
+// (x + y) / (2 (1 + u/3 + u^2/5 + u^3/7)).  Both branches are evaluated and
+// selected so that a wavefront never diverges here.
+template <typename real>
+__device__ __forceinline__ void lnmean_parts(real x, real y, real lx, real ly, real &num, real &den)
+{
+    const real s = x + y, d = x - y;
+    const real u = (d * d) / (s * s);
+    const bool series = u < LnMeanSwitch<real>::value;
+    const real poly = real(2) * (real(1) + u * (real(1) / real(3) + u * (real(1) / real(5) + u * (real(1) / real(7)))));
+    num = series ? s : (y - x);
+    den = series ? poly : (ly - lx);
+}
+template <typename real>
+__device__ __forceinline__ real lnmean(real x, real y, real lx, real ly)
+{
+    real n, d;
+    lnmean_parts(x, y, lx, ly, n, d);
+    return n / d;
+}
+template <typename real>
+__device__ __forceinline__ real inv_lnmean(real x, real y, real lx, real ly)
+{
+    real n, d;
+    lnmean_parts(x, y, lx, ly, n, d);
+    return d / n;
+}
+
+// ---------------------------------------------------------------- Euler
+// u = (rho, rho v_1 [, rho v_2], E), p = (gamma - 1)(E - rho |v|^2 / 2).
+// Fields: 0 rho, 1..DIM v, DIM+1 p, then per flux
+//   KG:      DIM+2 e = E/rho
+//   central: DIM+2 E
+//   Ranocha: DIM+2 ln rho, DIM+3 beta = rho/p, DIM+4 ln beta
+template <typename real, int DIM, int FLUX>
+struct EulerP {
+    static constexpr int M = DIM + 2;
+    static constexpr int NF = (FLUX == VOL_RANOCHA) ? DIM + 5 : DIM + 3;
+    static constexpr int P = DIM + 1;
+
+    __device__ __forceinline__ static void node(const real *u, real *nd, const Ctx<real> &c)
+    {
+        const real rho = u[0], irho = real(1) / rho;
+        real ke = real(0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            nd[1 + k] = u[1 + k] * irho;
+            ke += u[1 + k] * nd[1 + k];
+        }
+        const real p = c.gm1 * (u[DIM + 1] - real(0.5) * ke);
+        nd[0] = rho;
+        nd[P] = p;
+        if constexpr (FLUX == VOL_KG) {
+            nd[DIM + 2] = u[DIM + 1] * irho;
+        } else if constexpr (FLUX == VOL_CENTRAL) {
+            nd[DIM + 2] = u[DIM + 1];
+        } else {
+            const real beta = rho / p;
+            nd[DIM + 2] = dlog(rho);
+            nd[DIM + 3] = beta;
+            nd[DIM + 4] = dlog(beta);
+        }
+    }
+
+    // the fields that phys(), speed() and cons() read (no logarithms)
+    __device__ __forceinline__ static void node_basic(const real *u, real *nd, const Ctx<real> &c)
+    {
+        const real rho = u[0], irho = real(1) / rho;
+        real ke = real(0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            nd[1 + k] = u[1 + k] * irho;
+            ke += u[1 + k] * nd[1 + k];
+        }
+        nd[0] = rho;
+        nd[P] = c.gm1 * (u[DIM + 1] - real(0.5) * ke);
+        if constexpr (FLUX == VOL_KG) nd[DIM + 2] = u[DIM + 1] * irho;
+        else if constexpr (FLUX == VOL_CENTRAL) nd[DIM + 2] = u[DIM + 1];
+    }
+
+    __device__ __forceinline__ static real energy(const real *nd, const Ctx<real> &c)
+    {
+        if constexpr (FLUX == VOL_KG) return nd[0] * nd[DIM + 2];
+        if constexpr (FLUX == VOL_CENTRAL) return nd[DIM + 2];
+        real ke = real(0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ke += nd[1 + k] * nd[1 + k];
+        return nd[P] * c.inv_gm1 + real(0.5) * nd[0] * ke;
+    }
+
+    __device__ __forceinline__ static void cons(const real *nd, real *u, const Ctx<real> &c)
+    {
+        u[0] = nd[0];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) u[1 + k] = nd[0] * nd[1 + k];
+        u[DIM + 1] = energy(nd, c);
+    }
+
+    // physical flux from the fields (E recomputed for KG/Ranocha)
+    __device__ __forceinline__ static void phys(int d, const real *nd, real *f, const Ctx<real> &c)
+    {
+        const real vd = nd[1 + d], m = nd[0] * vd;
+        f[0] = m;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) f[1 + k] = m * nd[1 + k] + (k == d ? nd[P] : real(0));
+        f[DIM + 1] = (energy(nd, c) + nd[P]) * vd;
+    }
+
+    __device__ __forceinline__ static real speed(int d, const real *nd, const Ctx<real> &c)
+    {
+        return dabs(nd[1 + d]) + dsqrt(c.gamma * nd[P] / nd[0]);
+    }
+
+    __device__ __forceinline__ static void pair(int d, const real *a, const real *b, real *f, const Ctx<real> &c)
+    {
+        if constexpr (FLUX == VOL_CENTRAL) {
+            real fa[M], fb[M];
+            phys(d, a, fa, c);
+            phys(d, b, fb, c);
+#pragma unroll
+            for (int v = 0; v < M; ++v) f[v] = real(0.5) * (fa[v] + fb[v]);
+        } else if constexpr (FLUX == VOL_KG) {
+            const real rho = real(0.5) * (a[0] + b[0]);
+            const real vd = real(0.5) * (a[1 + d] + b[1 + d]);
+            const real p = real(0.5) * (a[P] + b[P]);
+            const real e = real(0.5) * (a[DIM + 2] + b[DIM + 2]);
+            const real m = rho * vd;
+            f[0] = m;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) f[1 + k] = m * (real(0.5) * (a[1 + k] + b[1 + k])) + (k == d ? p : real(0));
+            f[DIM + 1] = (rho * e + p) * vd;
+        } else {
+            const real rho_ln = lnmean(a[0], b[0], a[DIM + 2], b[DIM + 2]);
+            const real ibeta_ln = inv_lnmean(a[DIM + 3], b[DIM + 3], a[DIM + 4], b[DIM + 4]);
+            const real vd = real(0.5) * (a[1 + d] + b[1 + d]);
+            real vv = real(0);
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) vv += a[1 + k] * b[1 + k];
+            const real m = rho_ln * vd;
+            f[0] = m;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k)
+                f[1 + k] = m * (real(0.5) * (a[1 + k] + b[1 + k])) + (k == d ? real(0.5) * (a[P] + b[P]) : real(0));
+            f[DIM + 1] = m * (ibeta_ln * c.inv_gm1 + real(0.5) * vv) + real(0.5) * (a[P] * b[1 + d] + b[P] * a[1 + d]);
+        }
+    }
+};
+
+// ---------------------------------------------------------------- GLM-MHD
+// u = (rho, rho v (3), E, B (3), psi),
+// E = p/(gamma-1) + rho |v|^2/2 + |B|^2/2 + psi^2/2.
+// Fields: 0 rho, 1-3 v, 4 p, 5-7 B, 8 psi, 9 ln rho, 10 beta = rho/(2p),
+// 11 ln beta, 12 |v|^2, 13 |B|^2, 14 v.B
+template <typename real, int FLUX>
+struct MhdP {
+    static constexpr int M = 9;
+    static constexpr int NF = 15;
+
+    __device__ __forceinline__ static void node(const real *u, real *nd, const Ctx<real> &c)
+    {
+        const real rho = u[0], irho = real(1) / rho;
+        const real v1 = u[1] * irho, v2 = u[2] * irho, v3 = u[3] * irho;
+        const real B1 = u[5], B2 = u[6], B3 = u[7], psi = u[8];
+        const real vv = v1 * v1 + v2 * v2 + v3 * v3, BB = B1 * B1 + B2 * B2 + B3 * B3;
+        const real p = c.gm1 * (u[4] - real(0.5) * rho * vv - real(0.5) * BB - real(0.5) * psi * psi);
+        const real beta = real(0.5) * rho / p;
+        nd[0] = rho; nd[1] = v1; nd[2] = v2; nd[3] = v3; nd[4] = p;
+        nd[5] = B1; nd[6] = B2; nd[7] = B3; nd[8] = psi;
+        nd[9] = dlog(rho); nd[10] = beta; nd[11] = dlog(beta);
+        nd[12] = vv; nd[13] = BB; nd[14] = v1 * B1 + v2 * B2 + v3 * B3;
+    }
+
+    // the fields that phys(), speed(), fast(), btimes() and cons() read (no logarithms)
+    __device__ __forceinline__ static void node_basic(const real *u, real *nd, const Ctx<real> &c)
+    {
+        const real rho = u[0], irho = real(1) / rho;
+        const real v1 = u[1] * irho, v2 = u[2] * irho, v3 = u[3] * irho;
+        const real B1 = u[5], B2 = u[6], B3 = u[7], psi = u[8];
+        const real vv = v1 * v1 + v2 * v2 + v3 * v3, BB = B1 * B1 + B2 * B2 + B3 * B3;
+        nd[0] = rho; nd[1] = v1; nd[2] = v2; nd[3] = v3;
+        nd[4] = c.gm1 * (u[4] - real(0.5) * rho * vv - real(0.5) * BB - real(0.5) * psi * psi);
+        nd[5] = B1; nd[6] = B2; nd[7] = B3; nd[8] = psi;
+        nd[12] = vv; nd[13] = BB; nd[14] = v1 * B1 + v2 * B2 + v3 * B3;
+    }
+
+    __device__ __forceinline__ static void cons(const real *nd, real *u, const Ctx<real> &c)
+    {
+        u[0] = nd[0];
+        u[1] = nd[0] * nd[1]; u[2] = nd[0] * nd[2]; u[3] = nd[0] * nd[3];
+        u[4] = nd[4] * c.inv_gm1 + real(0.5) * nd[0] * nd[12] + real(0.5) * nd[13] + real(0.5) * nd[8] * nd[8];
+        u[5] = nd[5]; u[6] = nd[6]; u[7] = nd[7]; u[8] = nd[8];
+    }
+
+    __device__ __forceinline__ static void phys(int d, const real *nd, real *f, const Ctx<real> &c)
+    {
+        const real rho = nd[0], p = nd[4], psi = nd[8];
+        const real vd = nd[1 + d], Bd = nd[5 + d];
+        f[0] = rho * vd;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            f[1 + k] = rho * vd * nd[1 + k] - Bd * nd[5 + k] + (k == d ? p + real(0.5) * nd[13] : real(0));
+        f[4] = vd * (real(0.5) * rho * nd[12] + c.gamma * c.inv_gm1 * p + nd[13]) - Bd * nd[14] + c.ch * psi * Bd;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f[5 + k] = (k == d) ? c.ch * psi : vd * nd[5 + k] - Bd * nd[1 + k];
+        f[8] = c.ch * Bd;
+    }
+
+    // fast magnetosonic speed + |v_d| (without the cleaning speed)
+    __device__ __forceinline__ static real fast(int d, const real *nd, const Ctx<real> &c)
+    {
+        const real irho = real(1) / nd[0];
+        const real a2 = c.gamma * nd[4] * irho;
+        const real t = a2 + nd[13] * irho;
+        const real Bd = nd[5 + d];
+        const real cf = dsqrt(real(0.5) * (t + dsqrt(t * t - real(4) * a2 * Bd * Bd * irho)));
+        return dabs(nd[1 + d]) + cf;
+    }
+
+    __device__ __forceinline__ static real speed(int d, const real *nd, const Ctx<real> &c)
+    {
+        return dmax(fast(d, nd, c), c.ch);
+    }
+
+    // B_d(u_a) applied to g = (gB, gpsi): Powell phi_P = (0, B, v.B, v, 0),
+    // GLM phi_G = (0, 0, v_d psi, 0, v_d)
+    __device__ __forceinline__ static void btimes(int d, const real *nd, real gB, real gpsi, real *o)
+    {
+        o[0] = real(0);
+        o[1] = nd[5] * gB; o[2] = nd[6] * gB; o[3] = nd[7] * gB;
+        o[4] = nd[14] * gB + nd[1 + d] * nd[8] * gpsi;
+        o[5] = nd[1] * gB; o[6] = nd[2] * gB; o[7] = nd[3] * gB;
+        o[8] = nd[1 + d] * gpsi;
+    }
+
+    __device__ __forceinline__ static void pair(int d, const real *a, const real *b, real *f, const Ctx<real> &c)
+    {
+        if constexpr (FLUX == VOL_CENTRAL) {
+            real fa[M], fb[M];
+            phys(d, a, fa, c);
+            phys(d, b, fb, c);
+#pragma unroll
+            for (int v = 0; v < M; ++v) f[v] = real(0.5) * (fa[v] + fb[v]);
+            return;
+        }
+        const real h = real(0.5);
+        const real rho_ln = lnmean(a[0], b[0], a[9], b[9]);
+        const real ibeta_ln = inv_lnmean(a[10], b[10], a[11], b[11]);
+        const real rho_a = h * (a[0] + b[0]), beta_a = h * (a[10] + b[10]), psi_a = h * (a[8] + b[8]);
+        real va[3], Ba[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { va[k] = h * (a[1 + k] + b[1 + k]); Ba[k] = h * (a[5 + k] + b[5 + k]); }
+        const real f0 = rho_ln * va[d];
+        f[0] = f0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            f[1 + k] = f0 * va[k] - Ba[d] * Ba[k] + (k == d ? rho_a / (real(2) * beta_a) + h * h * (a[13] + b[13]) : real(0));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f[5 + k] = (k == d) ? c.ch * psi_a : va[d] * Ba[k] - va[k] * Ba[d];
+        f[8] = c.ch * Ba[d];
+        f[4] = f0 * (h * c.inv_gm1 * ibeta_ln - h * h * (a[12] + b[12]))
+             + f[1] * va[0] + f[2] * va[1] + f[3] * va[2]
+             + f[5] * Ba[0] + f[6] * Ba[1] + f[7] * Ba[2] + f[8] * psi_a
+             - h * h * (a[1 + d] * a[13] + b[1 + d] * b[13]) + Ba[d] * h * (a[14] + b[14])
+             - c.ch * h * (a[5 + d] * a[8] + b[5 + d] * b[8]);
+    }
+};
+
+} // namespace crk

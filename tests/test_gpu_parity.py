@@ -1,0 +1,295 @@
+"""GPU parity of the HIP cRKFR path with the FP64 CPU oracle.
+
+Every case steps the same seeded u^n with the same dt on both sides (the dt
+and blending coefficients fed to the GPU come from the oracle) and compares
+per conserved variable:  max|u_gpu - u_orc| / max|u_orc| <= 1e-12 (FP64)
+or <= 2e-5 (FP32 state and arithmetic against the FP64 oracle).  The GPU's
+own dt and blending coefficients are compared separately.  Sizes span
+several workgroups with a ragged last one."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2604_02125_amd import crk, inputs  # noqa: E402
+
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    crk.lib()
+
+
+def _pair(orc, **kw):
+    """Oracle problem and GPU solver for the same configuration."""
+    prec = kw.pop("precision", crk.FP64)
+    p = orc.Problem(**kw)
+    s = crk.Solver(dim=p.dim, nx=p.nx, ny=p.ny, x0=p.x0, x1=p.x1, y0=p.y0, y1=p.y1, degree=p.N,
+                   equation=p.eq, gamma=p.gamma, precision=prec, A=p.A, b=p.b, volume_flux=p.vol_flux,
+                   cfl=p.cfl, limiter=1 if p.limiter else 0, alpha_max=p.alpha_max, alpha_min=p.alpha_min)
+    return p, s
+
+
+def _rel(a, b):
+    """per-variable max-norm relative difference"""
+    a = np.asarray(a, dtype=np.float64)
+    return max(np.max(np.abs(a[v] - b[v])) / max(np.max(np.abs(b[v])), 1e-300) for v in range(b.shape[0]))
+
+
+def _gpu_step(s, u, dt, ch=0.0, alpha=None):
+    ug = torch.tensor(u, dtype=s.dtype, device="cuda")
+    out = s.new_state()
+    dtt = torch.tensor([dt, ch], dtype=torch.float64, device="cuda")
+    al = None if alpha is None else torch.tensor(alpha, dtype=torch.float64, device="cuda")
+    s.step(ug, out, dtt, alpha=al, compute_dt=False)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def _state(orc, p, seed):
+    xi, _ = orc.gll(p.N)
+    if p.eq == orc.MHD:
+        return inputs.perturb(inputs.orszag_tang(p.nx, p.ny, xi), seed, 1e-3)
+    if p.dim == 1:
+        return inputs.perturb(inputs.density_wave_1d(p.nx, xi), seed, 1e-3)
+    if p.x0 == -1.0:
+        return inputs.perturb(inputs.kelvin_helmholtz(p.nx, p.ny, xi), seed, 1e-3)
+    return inputs.random_smooth_euler(p.nx, p.ny, xi, seed=seed, amp=0.25)
+
+
+EULER2D = [(N, vol) for N in (1, 2, 3, 4) for vol in (0, 1, 2)]
+
+
+@pytest.mark.parametrize("N,vol", EULER2D)
+def test_euler2d_step_parity(orc, N, vol):
+    p, s = _pair(orc, dim=2, nx=13, ny=11, N=N, vol_flux=vol)
+    u = _state(orc, p, seed=100 + 10 * N + vol)
+    dt = orc.compute_dt(p, u)
+    ref, _ = orc.crk_step(p, u, dt)
+    got = _gpu_step(s, u, dt)
+    print(f"euler2d N={N} vol={vol}: rel={_rel(got, ref):.2e}")
+    assert _rel(got, ref) <= TOL64
+
+
+@pytest.mark.parametrize("N,vol", [(3, 2), (2, 1), (4, 0)])
+def test_euler1d_step_parity(orc, N, vol):
+    p, s = _pair(orc, dim=1, nx=37, N=N, vol_flux=vol)
+    u = _state(orc, p, seed=7)
+    dt = orc.compute_dt(p, u)
+    ref, _ = orc.crk_step(p, u, dt)
+    assert _rel(_gpu_step(s, u, dt), ref) <= TOL64
+
+
+@pytest.mark.parametrize("dim,N,vol", [(2, 3, 1), (2, 4, 2), (1, 3, 2)])
+def test_dt_parity(orc, dim, N, vol):
+    p, s = _pair(orc, dim=dim, nx=13, ny=11, N=N, vol_flux=vol)
+    u = _state(orc, p, seed=3)
+    dt = s.compute_dt(torch.tensor(u, device="cuda")).cpu().numpy()
+    assert abs(dt[0] - orc.compute_dt(p, u)) <= 1e-14 * dt[0]
+
+
+def test_traces_parity(orc):
+    """Local phase alone: U and F traces of every face node against the oracle."""
+    p, s = _pair(orc, dim=2, nx=9, ny=7, N=3, vol_flux=2)
+    u = _state(orc, p, seed=5)
+    dt = orc.compute_dt(p, u)
+    V, Ut, Ft, _ = orc.local_phase(p, u, dt)
+    ug = torch.tensor(u, device="cuda")
+    out, tr = s.new_state(), s.new_traces()
+    s.local_stages(ug, torch.tensor([dt, 0.0], device="cuda", dtype=torch.float64), out, tr)
+    torch.cuda.synchronize()
+    T = s.trace_view(tr).cpu().numpy()              # [face, c, e, k]
+    M = p.nvar
+    for face in range(4):
+        gU = T[face, :M].transpose(1, 2, 0)           # [e, k, v]
+        gF = T[face, M:2 * M].transpose(1, 2, 0)
+        gN = T[face, 2 * M:].transpose(1, 2, 0)
+        assert np.max(np.abs(gU - Ut[:, face])) <= 1e-13 * np.max(np.abs(Ut))
+        assert np.max(np.abs(gF - Ft[:, face])) <= 1e-13 * np.max(np.abs(Ft))
+        k = np.arange(4)
+        nodes = {0: k * 4, 1: k * 4 + 3, 2: k, 3: 12 + k}[face]
+        assert np.array_equal(gN, u[:, :, nodes].transpose(1, 2, 0))
+    # provisional state of the interior nodes is u^n - dt V exactly there
+    interior = [5, 6, 9, 10]
+    got = out.cpu().numpy()[:, :, interior]
+    assert _rel(got, (u - dt * V)[:, :, interior]) <= TOL64
+
+
+def test_blending_parity_khi(orc):
+    """Kelvin-Helmholtz with the blending limiter: GPU indicator against the
+    oracle's, and the step with the oracle's alpha fed in."""
+    p, s = _pair(orc, dim=2, nx=24, ny=20, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=1,
+                 limiter=orc.LIM_BLEND_MODAL)
+    u = _state(orc, p, seed=9)
+    araw_o, alpha_o, _ = orc.indicator(p, u)
+    assert alpha_o.max() > 0 and (alpha_o == 0).any()
+    araw_g, alpha_g = s.indicator(torch.tensor(u, device="cuda"))
+    assert np.max(np.abs(araw_g.cpu().numpy() - araw_o)) <= 1e-13
+    assert np.max(np.abs(alpha_g.cpu().numpy() - alpha_o)) <= 1e-13
+    dt = orc.compute_dt(p, u)
+    ref, _ = orc.crk_step(p, u, dt)
+    got = _gpu_step(s, u, dt, alpha=alpha_o)
+    assert _rel(got, ref) <= TOL64
+    # the GPU computing its own indicator inside the step gives the same result
+    ug = torch.tensor(u, device="cuda")
+    out = s.new_state()
+    s.step(ug, out, torch.tensor([dt, 0.0], dtype=torch.float64, device="cuda"), compute_dt=False)
+    assert _rel(out.cpu().numpy(), ref) <= TOL64
+
+
+@pytest.mark.parametrize("alpha_value", [0.0, 0.3, 1.0])
+def test_blending_uniform_alpha(orc, alpha_value):
+    p, s = _pair(orc, dim=2, nx=11, ny=9, N=3, vol_flux=2, limiter=orc.LIM_BLEND_GIVEN)
+    u = _state(orc, p, seed=11)
+    dt = 0.5 * orc.compute_dt(p, u)
+    a = np.full(p.nelem, alpha_value)
+    ref, _ = orc.crk_step(p, u, dt, a)
+    assert _rel(_gpu_step(s, u, dt, alpha=a), ref) <= TOL64
+
+
+@pytest.mark.parametrize("N,vol", [(3, 3), (4, 3), (3, 0), (2, 3)])
+def test_mhd_step_parity(orc, N, vol):
+    p, s = _pair(orc, dim=2, nx=10, ny=9, N=N, eq=orc.MHD, gamma=5.0 / 3.0, vol_flux=vol)
+    u = _state(orc, p, seed=21)
+    p.ch = orc.compute_ch(p, u)
+    dt = orc.compute_dt(p, u)
+    dtg = s.compute_dt(torch.tensor(u, device="cuda")).cpu().numpy()
+    assert abs(dtg[0] - dt) <= 1e-14 * dt and abs(dtg[1] - p.ch) <= 1e-14 * p.ch
+    ref, _ = orc.crk_step(p, u, dt)
+    got = _gpu_step(s, u, dt, ch=p.ch)
+    print(f"mhd N={N} vol={vol}: rel={_rel(got, ref):.2e}")
+    assert _rel(got, ref) <= TOL64
+
+
+@pytest.mark.parametrize("case", ["euler2d_kg", "euler2d_ranocha", "euler1d", "mhd"])
+def test_fp32_against_fp64_oracle(orc, case):
+    if case == "mhd":
+        p, s = _pair(orc, dim=2, nx=10, ny=9, N=4, eq=orc.MHD, gamma=5 / 3, vol_flux=3, precision=crk.FP32)
+    elif case == "euler1d":
+        p, s = _pair(orc, dim=1, nx=37, N=3, vol_flux=2, precision=crk.FP32)
+    else:
+        p, s = _pair(orc, dim=2, nx=13, ny=11, N=3, vol_flux=1 if case == "euler2d_kg" else 2, precision=crk.FP32)
+    u = _state(orc, p, seed=31)
+    if p.eq == orc.MHD:
+        p.ch = orc.compute_ch(p, u)
+    dt = orc.compute_dt(p, u)
+    ref, _ = orc.crk_step(p, u, dt)
+    # the oracle from the FP32-rounded input isolates the arithmetic error
+    u32 = u.astype(np.float32).astype(np.float64)
+    ref32, _ = orc.crk_step(p, u32, dt)
+    got = _gpu_step(s, u, dt, ch=p.ch)
+    # per-variable scale; the divergence-cleaning field psi starts at zero and
+    # stays small, so it is measured on the scale of the magnetic field
+    scale = np.array([np.max(np.abs(ref[v])) for v in range(p.nvar)])
+    if p.eq == orc.MHD:
+        scale[8] = np.max(np.abs(ref[5:8]))
+    err32 = np.array([np.max(np.abs(got[v] - ref32[v])) for v in range(p.nvar)]) / np.maximum(scale, 1e-300)
+    err = np.array([np.max(np.abs(got[v] - ref[v])) for v in range(p.nvar)]) / np.maximum(scale, 1e-300)
+    print(f"fp32 {case}: per-variable rel err (arith) {np.array2string(err32, precision=2)}")
+    assert err32.max() <= TOL32
+    assert err.max() <= TOL32
+
+
+def test_oracle_trajectory_parity_density_wave(orc):
+    """Config-1 workload (1D Euler, 64 elements, N=3, Ranocha, CFL 0.4): per
+    step from the oracle's own trajectory at steps 0, 1, 100 and 199, and the
+    200-step GPU trajectory against the oracle's."""
+    p, s = _pair(orc, dim=1, nx=64, N=3, vol_flux=2)
+    xi, _ = orc.gll(3)
+    u = inputs.density_wave_1d(64, xi)
+    traj = [u]
+    for _ in range(200):
+        traj.append(orc.crk_step(p, traj[-1], orc.compute_dt(p, traj[-1]))[0])
+    for k in (0, 1, 100, 199):
+        dt = orc.compute_dt(p, traj[k])
+        assert _rel(_gpu_step(s, traj[k], dt), traj[k + 1]) <= TOL64
+    ug = torch.tensor(u, device="cuda")
+    buf = [ug, s.new_state()]
+    dt = s.new_dt()
+    for n in range(200):
+        s.step(buf[n % 2], buf[(n + 1) % 2], dt)
+    torch.cuda.synchronize()
+    assert _rel(buf[0].cpu().numpy(), traj[200]) <= 1e-11
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 5), (6, 1), (2, 2)])
+def test_tiny_and_degenerate_meshes(orc, nx, ny):
+    """Self-periodic elements (a neighbour is the element itself)."""
+    p, s = _pair(orc, dim=2, nx=nx, ny=ny, N=3, vol_flux=2)
+    u = _state(orc, p, seed=41)
+    dt = orc.compute_dt(p, u)
+    ref, _ = orc.crk_step(p, u, dt)
+    assert _rel(_gpu_step(s, u, dt), ref) <= TOL64
+
+
+def test_free_stream_and_conservation_gpu(orc):
+    p, s = _pair(orc, dim=2, nx=16, ny=16, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=1,
+                 limiter=orc.LIM_BLEND_MODAL)
+    c = np.zeros(p.shape)
+    c[0], c[1], c[2], c[3] = 1.3, 0.2, -0.4, 3.0
+    got = _gpu_step(s, c, orc.compute_dt(p, c))
+    assert np.max(np.abs(got - c)) <= 1e-14 * 3.0
+    u = torch.tensor(_state(orc, p, seed=43), device="cuda")
+    d0 = s.diagnostics(u).cpu().numpy()
+    assert np.allclose(d0[:4], orc.diagnostics(p, u.cpu().numpy())["totals"], rtol=1e-13, atol=1e-15)
+    out = s.new_state()
+    s.step(u, out, s.new_dt())
+    d1 = s.diagnostics(out).cpu().numpy()
+    assert np.max(np.abs(d1[:4] - d0[:4])) <= 1e-14 * np.max(np.abs(d0[:4]))
+
+
+def test_diagnostics_parity(orc):
+    p, s = _pair(orc, dim=2, nx=13, ny=11, N=3, vol_flux=1)
+    u = _state(orc, p, seed=45)
+    u[3, 17, 5] = -1.0            # negative pressure in element 17
+    u[0, 40, 2] = np.nan          # non-finite in element 40
+    d = s.diagnostics(torch.tensor(u, device="cuda")).cpu().numpy()
+    o = orc.diagnostics(p, u)
+    M = p.nvar
+    assert d[M + 3] == o["nonfinite"] == 1
+    assert d[M + 4] == o["first_bad"] == 17
+    u[0, 40, 2] = 1.0
+    u[3, 17, 5] = u[3, 17, 4]
+    d = s.diagnostics(torch.tensor(u, device="cuda")).cpu().numpy()
+    o = orc.diagnostics(p, u)
+    assert np.allclose(d[:M], o["totals"], rtol=1e-13, atol=1e-15)
+    assert abs(d[M] - o["entropy"]) <= 1e-12 * abs(o["entropy"])
+    assert d[M + 1] == o["min_rho"] and abs(d[M + 2] - o["min_p"]) <= 1e-14 * o["min_p"] and d[M + 4] == -1
+
+
+def test_deterministic(orc):
+    p, s = _pair(orc, dim=2, nx=32, ny=32, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=1,
+                 limiter=orc.LIM_BLEND_MODAL)
+    u = torch.tensor(_state(orc, p, seed=47), device="cuda")
+    outs = []
+    for _ in range(2):
+        o = s.new_state()
+        s.step(u, o, s.new_dt())
+        outs.append(o.clone())
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_full_size_khi_parity(orc):
+    """The benchmarked workload (2D Euler Kelvin-Helmholtz, 256x256 elements,
+    N=3, Kennedy-Gruber, blending) in the benchmark's launch configuration:
+    one step, every element compared with the oracle."""
+    p, s = _pair(orc, dim=2, nx=256, ny=256, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=1,
+                 limiter=orc.LIM_BLEND_MODAL, nthreads=16)
+    xi, _ = orc.gll(3)
+    u = inputs.kelvin_helmholtz(256, 256, xi)
+    dt = orc.compute_dt(p, u)
+    ref, alpha = orc.crk_step(p, u, dt)
+    ug = torch.tensor(u, device="cuda")
+    out = s.new_state()
+    dtg = s.new_dt()
+    s.step(ug, out, dtg)
+    torch.cuda.synchronize()
+    assert abs(dtg[0].item() - dt) <= 1e-14 * dt
+    got = out.cpu().numpy()
+    print(f"full size rel={_rel(got, ref):.2e}, alpha>0 in {np.count_nonzero(alpha)} elements")
+    assert _rel(got, ref) <= TOL64
