@@ -6,7 +6,8 @@ Workload (default): 2D compressible Euler, Kelvin-Helmholtz initial data on
 classical RK4 inner stages, CFL 0.4, subcell-FV blending limiter with
 alpha_max = 0.008, FP64.  One step = CFL time step reduction + blending
 indicator + local stages + interface exchange and final update, with the
-state resident in HBM.  Metric: DOF-updates/s (one DOF = one solution node).
+state resident in HBM; the time-step reduction and the indicator of the
+new state run inside the interface phase (pipelined step).  Metric: DOF-updates/s (one DOF = one solution node).
 
 Prints one JSON line.  ``--gpus`` above 1 is rejected: this build runs on a
 single GPU.
@@ -27,6 +28,25 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 
+# HBM bytes per launch of k_local measured by rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE, scaled by the plain-copy calibration (read x2.0, write x1.0);
+# valid only for the kernel sources whose digest is recorded with it.
+MEASURED_TRAFFIC = {
+    ("khi256", "fp64"): {"sources_sha256": "e9752acc560995176e5fd6f9f738a68afc7257adb1bf16f0633f4e15363ca0f9",
+                         "bytes": (2.0 * 17253.9 + 1.0 * 98816.1) * 1024},
+}
+KERNEL_SOURCES = ("paper_2604_02125_amd/csrc/crk_kernels.hpp", "paper_2604_02125_amd/csrc/crk_physics.hpp")
+
+
+def sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 WORKLOADS = {
     "khi256": dict(nx=256, ny=256, degree=3, flux=1, limiter=1,
                    desc="2D Euler Kelvin-Helmholtz 256x256, N=3, Kennedy-Gruber, blending alpha_max=0.008"),
@@ -37,10 +57,10 @@ WORKLOADS = {
 
 def k2_bytes_per_dof(M: int, dim: int, N: int, elem: int) -> float:
     """Algorithmic HBM bytes of the local-stage kernel per DOF: read u^n, write
-    the provisional state, write the face traces (U, F, u^n: 3M values per face
+    the provisional state, write the face traces (U, F: 2M values per face
     node, 2*dim faces of (N+1)^(dim-1) nodes per element)."""
     npe = (N + 1) ** dim
-    traces = 2 * dim * (N + 1) ** (dim - 1) * 3 * M
+    traces = 2 * dim * (N + 1) ** (dim - 1) * 2 * M
     return elem * (2 * M + traces / npe)
 
 
@@ -53,6 +73,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (no multi-GPU path in this build); use --gpus 1", file=sys.stderr)
@@ -60,6 +82,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8, "copies": 5}))
+        return
 
     from paper_2604_02125_amd import crk, inputs
 
@@ -76,9 +108,6 @@ def main():
     ndof = E * NP
     buf = [torch.tensor(u0, dtype=s.dtype, device="cuda"), s.new_state()]
     dt = s.new_dt()
-    araw = torch.empty(E, dtype=torch.float64, device="cuda")
-    alpha = torch.empty(E, dtype=torch.float64, device="cuda")
-    tr = s.new_traces()
     stream = torch.cuda.current_stream()
     L = crk.lib()
     h = s._h
@@ -86,16 +115,17 @@ def main():
     sp = crk._stream(stream)
 
     def step(n, ev=None):
+        # pipelined step: dt and the blending indicator of the new state are
+        # computed by the interface phase (crk_prepare seeded them for u0)
         ui, uo = buf[n % 2], buf[(n + 1) % 2]
-        crk._check(L.crk_compute_dt(h, ptr(ui), ptr(dt), sp), "dt")
-        crk._check(L.crk_indicator(h, ptr(ui), ptr(araw), ptr(alpha), sp), "indicator")
         if ev is not None:
             ev[0].record(stream)
-        crk._check(L.crk_local_stages(h, ptr(ui), ptr(dt), ptr(alpha), ptr(uo), ptr(tr), sp), "local")
+        crk._check(L.crk_advance(h, ptr(ui), ptr(uo), ptr(dt), crk.PHASE_LOCAL, sp), "advance/local")
         if ev is not None:
             ev[1].record(stream)
-        crk._check(L.crk_interface_update(h, ptr(tr), ptr(dt), ptr(alpha), ptr(uo), sp), "interface")
+        crk._check(L.crk_advance(h, ptr(ui), ptr(uo), ptr(dt), crk.PHASE_INTERFACE, sp), "advance/interface")
 
+    crk._check(L.crk_prepare(h, ptr(buf[0]), ptr(dt), sp), "prepare")
     for n in range(args.warmup):
         step(n)
     torch.cuda.synchronize()
@@ -115,6 +145,8 @@ def main():
     value = ndof * args.steps / elapsed
     kb = k2_bytes_per_dof(M, 2, w["degree"], elem) * ndof
     achieved = kb / (k2_ms * 1e-3) / 1e9
+    rec = MEASURED_TRAFFIC.get((args.workload, args.precision))
+    traffic = rec["bytes"] if rec and rec["sources_sha256"] == sources_digest() else None
     out = {
         "metric": "DOF-updates/s at 1 GPU",
         "value": value,
@@ -132,7 +164,7 @@ def main():
                    "precision": args.precision, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_local (local stages)", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": None, "kernel_ms": k2_ms,
+                     "traffic": traffic, "kernel_ms": k2_ms,
                      "algorithmic_bytes_per_launch": kb},
     }
     if not args.no_cpu_baseline:

@@ -97,9 +97,10 @@ crk_status crk_state_layout(const crk_solver *s, int64_t *nvar, int64_t *nelem, 
 
 /* Face traces handed from the local-stage phase to the interface phase:
  * trace[face][c][e][k] with face = 2*d + side (side 0: xi_d = 0, side 1:
- * xi_d = 1), c < 3*nvar: U = sum_j b_j u^(j) (c < nvar), F = sum_j b_j
- * f_d(u^(j)) (nvar <= c < 2 nvar), u^n (2 nvar <= c < 3 nvar); k = face node
- * (j for x faces, i for y faces; 0 in 1D).  Element type = the precision. */
+ * xi_d = 1), c < 2*nvar: U = sum_j b_j u^(j) (c < nvar), F = sum_j b_j
+ * f_d(u^(j)) (nvar <= c < 2 nvar) (eq:disc.avg.flux at the face nodes);
+ * k = face node (j for x faces, i for y faces; 0 in 1D).  Element type =
+ * the precision. */
 crk_status crk_trace_bytes(const crk_solver *s, size_t *bytes);
 
 /* Scratch for crk_step and the reductions (traces, blending coefficients,
@@ -135,13 +136,14 @@ crk_status crk_local_stages(crk_solver *s, const void *u_in, const double *dt_de
                             void *u_out, void *traces, crk_stream stream);
 
 /* Interface phase (eq:numflux.cons, eq:crkfr.non.cons.final): Rusanov flux
- * of the time averages with lambda from the u^n traces of both sides,
- * blended with the first-order flux of u^n by a = (alpha_e + alpha_nb)/2
- * when alpha != NULL, MHD flux 1/2 B(u^n_own)(g(U^-) + g(U^+)), and the
- * lifting with dg_R/dxi = delta_pN/w_N, dg_L/dxi = -delta_p0/w_0 applied to
- * u_inout in place. */
-crk_status crk_interface_update(crk_solver *s, const void *traces, const double *dt_dev, const double *alpha,
-                                void *u_inout, crk_stream stream);
+ * of the time averages with lambda from u^n (u_in, the state the step
+ * started from) on both sides of each face node, blended with the
+ * first-order flux of u^n by a = (alpha_e + alpha_nb)/2 when alpha != NULL,
+ * MHD flux 1/2 B(u^n_own)(g(U^-) + g(U^+)), and the lifting with
+ * dg_R/dxi = delta_pN/w_N, dg_L/dxi = -delta_p0/w_0 applied to the face
+ * nodes of u_inout in place (u_inout = the local phase's output). */
+crk_status crk_interface_update(crk_solver *s, const void *u_in, const void *traces, const double *dt_dev,
+                                const double *alpha, void *u_inout, crk_stream stream);
 
 /* One full cRKFR step u_out = step(u_in).  flags & CRK_STEP_COMPUTE_DT:
  * compute dt_dev from u_in first (else dt_dev is an input).  With the
@@ -151,6 +153,22 @@ crk_status crk_interface_update(crk_solver *s, const void *traces, const double 
 #define CRK_STEP_COMPUTE_DT 1
 crk_status crk_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, const double *alpha_in,
                     int flags, crk_stream stream);
+
+/* Pipelined time stepping.  crk_prepare computes, for a state u, dt_dev
+ * (as crk_compute_dt) and, with the limiter on, the raw blending indicator
+ * of u, kept in the workspace.  crk_advance then performs one step
+ * u_out = step(u_in) using dt_dev and the kept indicator, both of which must
+ * belong to u_in (from crk_prepare or from the previous crk_advance), and
+ * computes them for u_out while the new state is still in registers: on
+ * return dt_dev holds the time step of u_out.  The step is the same
+ * arithmetic as crk_step; only the CFL reduction and the indicator move
+ * into the interface phase.  `phases` selects CRK_PHASE_LOCAL and/or
+ * CRK_PHASE_INTERFACE (both = one full step; the phases of one step must
+ * be issued in this order on one stream).  Needs the workspace. */
+#define CRK_PHASE_LOCAL 1
+#define CRK_PHASE_INTERFACE 2
+crk_status crk_prepare(crk_solver *s, const void *u, double *dt_dev, crk_stream stream);
+crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, int phases, crk_stream stream);
 
 /* FP64 diagnostics of u into out_dev (device, nvar + 5 doubles):
  * totals sum_e sum_p w_p u_p |Omega_e| (nvar), total entropy

@@ -21,6 +21,7 @@ VOL_CENTRAL, VOL_KG, VOL_RANOCHA, VOL_DERIGS = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 LIM_NONE, LIM_BLEND = 0, 1
 STEP_COMPUTE_DT = 1
+PHASE_LOCAL, PHASE_INTERFACE = 1, 2
 
 
 class MeshDesc(C.Structure):
@@ -71,9 +72,11 @@ def lib():
             "crk_compute_dt": (st, [_vp, _vp, _vp, _vp]),
             "crk_indicator": (st, [_vp, _vp, _vp, _vp, _vp]),
             "crk_local_stages": (st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-            "crk_interface_update": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
+            "crk_interface_update": (st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "crk_step": (st, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp]),
             "crk_diagnostics": (st, [_vp, _vp, _vp, _vp]),
+            "crk_prepare": (st, [_vp, _vp, _vp, _vp]),
+            "crk_advance": (st, [_vp, _vp, _vp, _vp, C.c_int, _vp]),
             "crk_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -166,7 +169,7 @@ class Solver:
     def trace_view(self, traces):
         """[face, c, e, k] view of a trace buffer."""
         nf = self.degree + 1 if self.dim == 2 else 1
-        return traces.view(2 * self.dim, 3 * self.shape[0], self.nelem, nf)
+        return traces.view(2 * self.dim, 2 * self.shape[0], self.nelem, nf)
 
     def _check_state(self, u):
         if u.dtype != self.dtype or tuple(u.shape) != self.shape or not u.is_contiguous() or u.device.type != "cuda":
@@ -193,16 +196,27 @@ class Solver:
         _check(lib().crk_local_stages(self._h, _ptr(u_in), _ptr(dt), _ptr(alpha), _ptr(u_out), _ptr(traces),
                                       _stream(stream)), "crk_local_stages")
 
-    def interface_update(self, traces, dt, u, alpha=None, stream=None):
+    def interface_update(self, u_in, traces, dt, u, alpha=None, stream=None):
+        self._check_state(u_in)
         self._check_state(u)
-        _check(lib().crk_interface_update(self._h, _ptr(traces), _ptr(dt), _ptr(alpha), _ptr(u), _stream(stream)),
-               "crk_interface_update")
+        _check(lib().crk_interface_update(self._h, _ptr(u_in), _ptr(traces), _ptr(dt), _ptr(alpha), _ptr(u),
+                                          _stream(stream)), "crk_interface_update")
 
     def step(self, u_in, u_out, dt, alpha=None, compute_dt=True, stream=None):
         self._check_state(u_in)
         self._check_state(u_out)
         _check(lib().crk_step(self._h, _ptr(u_in), _ptr(u_out), _ptr(dt), _ptr(alpha),
                               STEP_COMPUTE_DT if compute_dt else 0, _stream(stream)), "crk_step")
+
+    def prepare(self, u, dt, stream=None):
+        self._check_state(u)
+        _check(lib().crk_prepare(self._h, _ptr(u), _ptr(dt), _stream(stream)), "crk_prepare")
+
+    def advance(self, u_in, u_out, dt, phases=PHASE_LOCAL | PHASE_INTERFACE, stream=None):
+        self._check_state(u_in)
+        self._check_state(u_out)
+        _check(lib().crk_advance(self._h, _ptr(u_in), _ptr(u_out), _ptr(dt), int(phases), _stream(stream)),
+               "crk_advance")
 
     def diagnostics(self, u, stream=None):
         import torch

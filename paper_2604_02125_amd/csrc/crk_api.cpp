@@ -119,6 +119,7 @@ struct crk_solver {
     size_t state_bytes, trace_bytes;
     size_t off_partials, off_araw, off_alpha, off_traces, ws_bytes;
     char *ws;
+    bool prepared;   // crk_prepare has initialised the pipelined-step state of this workspace
 };
 
 namespace {
@@ -230,6 +231,8 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     diff_matrix(t.N, xi, D);
     for (int p = 0; p <= t.N; ++p) {
         t.w[p] = w[p];
+        t.invw_dx[0][p] = t.invdx[0] / w[p];
+        t.invw_dx[1][p] = t.invdx[1] / w[p];
         for (int q = 0; q <= t.N; ++q) t.D[p][q] = D[p * (t.N + 1) + q];
     }
     modal_inverse(t.N, xi, w, t.Vinv);
@@ -240,14 +243,17 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
 
     s->elem_bytes = s->prec == CRK_FP64 ? 8 : 4;
     s->state_bytes = (size_t)t.M * nelem * nnode * s->elem_bytes;
-    s->trace_bytes = (size_t)2 * t.dim * 3 * t.M * nelem * t.nface * s->elem_bytes;
+    s->trace_bytes = (size_t)2 * t.dim * 2 * t.M * nelem * t.nface * s->elem_bytes;
     size_t off = 0;
-    s->off_partials = off; off = align256(off + sizeof(double) * RED_BLOCKS * 16);
+    const long elem_blocks = (nelem + (BLOCK / nnode) - 1) / (BLOCK / nnode);
+    const long nparts = elem_blocks > RED_BLOCKS * 16 ? elem_blocks : RED_BLOCKS * 16;
+    s->off_partials = off; off = align256(off + sizeof(double) * nparts);
     s->off_araw = off; off = align256(off + sizeof(double) * nelem);
     s->off_alpha = off; off = align256(off + sizeof(double) * nelem);
     s->off_traces = off; off = align256(off + s->trace_bytes);
     s->ws_bytes = off;
     s->ws = nullptr;
+    s->prepared = false;
     *out = s;
     return CRK_OK;
 }
@@ -288,6 +294,7 @@ crk_status crk_set_workspace(crk_solver *s, void *dev, size_t bytes)
     if (!is_aligned(dev)) return fail(CRK_ERR_ARG, "workspace must be 256-byte aligned");
     if (bytes < s->ws_bytes) return fail(CRK_ERR_ARG, "workspace too small");
     s->ws = (char *)dev;
+    s->prepared = false;
     return CRK_OK;
 }
 
@@ -321,17 +328,23 @@ crk_status crk_local_stages(crk_solver *s, const void *u_in, const double *dt_de
     if (!s || !u_in || !dt_dev || !u_out || !traces) return fail(CRK_ERR_ARG, "null argument");
     if (u_in == u_out) return fail(CRK_ERR_ARG, "u_in and u_out must not alias");
     if (!is_aligned(u_in) || !is_aligned(u_out) || !is_aligned(traces)) return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
-    StepPtrs p{u_in, u_out, dt_dev, s->limiter == CRK_LIM_BLEND ? alpha : nullptr, traces};
+    StepPtrs p{};
+    p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = traces;
+    p.alpha = s->limiter == CRK_LIM_BLEND ? alpha : nullptr;
     hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::local(s->t, s->flux, p, (hipStream_t)stream); });
     return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_local_stages");
 }
 
-crk_status crk_interface_update(crk_solver *s, const void *traces, const double *dt_dev, const double *alpha,
-                                void *u_inout, crk_stream stream)
+crk_status crk_interface_update(crk_solver *s, const void *u_in, const void *traces, const double *dt_dev,
+                                const double *alpha, void *u_inout, crk_stream stream)
 {
-    if (!s || !traces || !dt_dev || !u_inout) return fail(CRK_ERR_ARG, "null argument");
-    if (!is_aligned(u_inout) || !is_aligned(traces)) return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
-    StepPtrs p{nullptr, u_inout, dt_dev, s->limiter == CRK_LIM_BLEND ? alpha : nullptr, const_cast<void *>(traces)};
+    if (!s || !u_in || !traces || !dt_dev || !u_inout) return fail(CRK_ERR_ARG, "null argument");
+    if (u_in == u_inout) return fail(CRK_ERR_ARG, "u_in and u_inout must not alias");
+    if (!is_aligned(u_in) || !is_aligned(u_inout) || !is_aligned(traces))
+        return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
+    StepPtrs p{};
+    p.u_in = u_in; p.u_out = u_inout; p.dt = dt_dev; p.traces = const_cast<void *>(traces);
+    p.alpha = s->limiter == CRK_LIM_BLEND ? alpha : nullptr;
     hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::interface(s->t, s->flux, p, (hipStream_t)stream); });
     return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_interface_update");
 }
@@ -361,7 +374,52 @@ crk_status crk_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev
     void *tr = s->ws + s->off_traces;
     st = crk_local_stages(s, u_in, dt_dev, alpha, u_out, tr, stream);
     if (st) return st;
-    return crk_interface_update(s, tr, dt_dev, alpha, u_out, stream);
+    return crk_interface_update(s, u_in, tr, dt_dev, alpha, u_out, stream);
+}
+
+crk_status crk_prepare(crk_solver *s, const void *u, double *dt_dev, crk_stream stream)
+{
+    crk_status st = crk_compute_dt(s, u, dt_dev, stream);
+    if (st) return st;
+    if (s->limiter == CRK_LIM_BLEND) st = crk_indicator(s, u, (double *)(s->ws + s->off_araw), nullptr, stream);
+    if (st) return st;
+    s->prepared = true;
+    return CRK_OK;
+}
+
+crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, int phases, crk_stream stream)
+{
+    crk_status st = need_ws(s);
+    if (st) return st;
+    if (!u_in || !u_out || !dt_dev) return fail(CRK_ERR_ARG, "null pointer");
+    if (u_in == u_out) return fail(CRK_ERR_ARG, "u_in and u_out must not alias");
+    if (!is_aligned(u_in) || !is_aligned(u_out)) return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
+    if (phases & ~(CRK_PHASE_LOCAL | CRK_PHASE_INTERFACE)) return fail(CRK_ERR_ARG, "unknown phase bits");
+    if (!s->prepared) return fail(CRK_ERR_STATE, "crk_prepare must run before crk_advance");
+    const bool lim = s->limiter == CRK_LIM_BLEND;
+    double *araw = (double *)(s->ws + s->off_araw);
+    double *alpha = (double *)(s->ws + s->off_alpha);
+    void *tr = s->ws + s->off_traces;
+    hipError_t e = hipSuccess;
+    if (phases & CRK_PHASE_LOCAL) {
+        StepPtrs p{};
+        p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = tr;
+        p.alpha_raw = lim ? araw : nullptr;
+        p.alpha_s = alpha;
+        e = dispatch(s, [&](auto fam) { return decltype(fam)::local(s->t, s->flux, p, (hipStream_t)stream); });
+        if (e != hipSuccess) return hip_fail(e, "crk_advance (local phase)");
+    }
+    if (phases & CRK_PHASE_INTERFACE) {
+        StepPtrs p{};
+        p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = tr;
+        p.alpha = lim ? alpha : nullptr;
+        p.alpha_raw_out = lim ? araw : nullptr;
+        p.partials = (double *)(s->ws + s->off_partials);
+        p.dt_out = dt_dev;
+        e = dispatch(s, [&](auto fam) { return decltype(fam)::interface(s->t, s->flux, p, (hipStream_t)stream); });
+        if (e != hipSuccess) return hip_fail(e, "crk_advance (interface phase)");
+    }
+    return CRK_OK;
 }
 
 crk_status crk_diagnostics(crk_solver *s, const void *u, double *out_dev, crk_stream stream)

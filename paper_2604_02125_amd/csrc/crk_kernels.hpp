@@ -28,6 +28,7 @@ struct Tables {
     double b[MAXS];
     double D[MAXN + 1][MAXN + 1];     // D_pq = l_q'(xi_p) on [0,1]
     double w[MAXN + 1];               // GLL weights on [0,1]
+    double invw_dx[2][MAXN + 1];      // 1/(w_p dx_d)
     double Vinv[MAXN + 1][MAXN + 1];  // nodal -> orthonormal Legendre modal
     double cfl;
     double ind_threshold, ind_sharpness, alpha_min, alpha_max;
@@ -39,6 +40,14 @@ struct StepPtrs {
     const double *dt;      // [dt, c_h]
     const double *alpha;   // final blending coefficients or nullptr
     void *traces;
+    // pipelined step (crk_advance): the local phase smooths the raw indicator
+    // of u_in itself; the interface phase computes dt and the raw indicator
+    // of u_out while the new state is in registers.
+    const double *alpha_raw;  // local phase: raw indicator of u_in, or nullptr
+    double *alpha_s;          // local phase: smoothed coefficients written for the interface phase
+    double *alpha_raw_out;    // interface phase: raw indicator of u_out, or nullptr
+    double *partials;         // interface phase: per-workgroup wave-speed maxima
+    double *dt_out;           // interface phase: dt and c_h of u_out (finished by k_dt_final), or nullptr
 };
 
 // ---------------------------------------------------------------- helpers
@@ -49,6 +58,28 @@ __device__ __forceinline__ long neighbour(const Tables &t, long e, int d, int si
     if (d == 0) ex = side ? (ex + 1 == t.nx ? 0 : ex + 1) : (ex == 0 ? t.nx - 1 : ex - 1);
     else ey = side ? (ey + 1 == t.ny ? 0 : ey + 1) : (ey == 0 ? t.ny - 1 : ey - 1);
     return ey * t.nx + ex;
+}
+
+// element coordinates and the four (two in 1D) face neighbours with one division
+struct Nbrs {
+    long n[2][2];   // [d][side]
+};
+__device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
+{
+    Nbrs r;
+    if (t.dim == 1) {
+        r.n[0][0] = e == 0 ? t.nx - 1 : e - 1;
+        r.n[0][1] = e + 1 == t.nx ? 0 : e + 1;
+        r.n[1][0] = r.n[1][1] = e;
+        return r;
+    }
+    const long ey = e / t.nx, ex = e - ey * t.nx;
+    const long row = ey * t.nx;
+    r.n[0][0] = row + (ex == 0 ? t.nx - 1 : ex - 1);
+    r.n[0][1] = row + (ex + 1 == t.nx ? 0 : ex + 1);
+    r.n[1][0] = (ey == 0 ? (long)(t.ny - 1) * t.nx : row - t.nx) + ex;
+    r.n[1][1] = (ey + 1 == t.ny ? 0 : row + t.nx) + ex;
+    return r;
 }
 
 template <typename real, int EQ, int DIM, int FLUX> struct PhysOf;
@@ -67,11 +98,24 @@ __device__ __forceinline__ Ctx<real> make_ctx(const Tables &t, const double *dt)
 }
 
 // ---------------------------------------------------------------- K2: local stages
-// For every element: s inner stages u^(i) = u^n - dt sum_{j<i} a_ij R^(j)
+// For every element: S inner stages u^(i) = u^n - dt sum_{j<i} a_ij R^(j)
 // with R^(i)_p = sum_d 1/dx_d sum_q [2 D_pq f_S,d(u_p,u_q) + D_pq B_d(u_p) g_d(u_q)]
 // (eq:crkfr.inner with the volume terms of Section 3); V = sum_j b_j R^(j);
 // face traces U, F; provisional update u* (see crk_local_stages).
-template <typename real, int EQ, int DIM, int N, int FLUX>
+//
+// Pairs along a line are visited by rotation: lane p pairs with
+// q = (p + k) mod (N+1), k = 1..N.  Rotation k and N+1-k visit the same
+// unordered pairs, so for Euler each lane evaluates only the rotations
+// k < (N+1)/2 (and k = (N+1)/2 when N+1 is even) and takes the mirrored
+// fluxes f_S(u_p, u_q) = f_S(u_q, u_p) from its line neighbour through LDS.
+template <int N, int DIM>
+__device__ __forceinline__ int line_node(const int *pd, int d, int qd)
+{
+    constexpr int n1 = N + 1;
+    return (DIM == 1) ? qd : (d == 0 ? pd[1] * n1 + qd : qd * n1 + pd[0]);
+}
+
+template <typename real, int EQ, int DIM, int N, int FLUX, int S>
 __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs a)
 {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
@@ -80,7 +124,12 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
     constexpr int EPB = BLOCK / NP;
     constexpr int M = Phys::M;
     constexpr int NF = Phys::NF;
+    constexpr bool SYM = (EQ == EQ_EULER) && (N >= 2);
+    constexpr int NPRIM = SYM ? (n1 - 1) / 2 : 0;          // rotations whose mirror comes from LDS
+    constexpr int KSELF = (SYM && n1 % 2 == 0) ? n1 / 2 : 0; // self-mirrored rotation, evaluated directly
+    constexpr int NX = SYM ? DIM * NPRIM * M : 1;
     __shared__ real lds[NF][BLOCK];
+    __shared__ real xch[NX][BLOCK];
 
     const int tid = threadIdx.x;
     int le = tid / NP;
@@ -94,11 +143,10 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
     const long E = t.nelem;
 
     const Ctx<real> ctx = make_ctx<real>(t, a.dt);
-    const double dt = a.dt[0];
-    const real rdt = real(dt);
+    const real rdt = real(a.dt[0]);
 
-    // per-lane coefficients: for rotation k = 1..N the neighbour q = (p_d + k) mod (N+1)
-    real Dk[DIM][N > 0 ? N : 1], Ddiag[DIM], invw[DIM];
+    // per-lane coefficients 2 D_{p,q}/dx_d of rotation k = 1..N, of the diagonal, and 1/(w_p dx_d)
+    real Dk[DIM][N], Ddiag[DIM], invw[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
 #pragma unroll
@@ -112,7 +160,7 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
         real dg = real(0), iw = real(0);
 #pragma unroll
         for (int r = 0; r < n1; ++r)
-            if (pd[d] == r) { dg = real(2.0 * t.D[r][r] * t.invdx[d]); iw = real(t.invdx[d] / t.w[r]); }
+            if (pd[d] == r) { dg = real(2.0 * t.D[r][r] * t.invdx[d]); iw = real(t.invw_dx[d][r]); }
         Ddiag[d] = dg;
         invw[d] = iw;
     }
@@ -136,10 +184,24 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
 #pragma unroll
     for (int v = 0; v < M; ++v) un[v] = uin[((long)v * E + es) * NP + node];
 
-    const real alpha = (a.alpha != nullptr && valid) ? real(a.alpha[es]) : real(0);
-    const bool blend = a.alpha != nullptr;
+    bool blend;
+    real alpha;
+    if (a.alpha_raw != nullptr) {
+        // alpha_e = max(alpha_raw_e, max over face neighbours of alpha_raw / 2)
+        blend = true;
+        double am = a.alpha_raw[es];
+        const Nbrs nb = neighbours(t, es);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd) am = fmax(am, 0.5 * a.alpha_raw[nb.n[d][sd]]);
+        alpha = valid ? real(am) : real(0);
+        if (valid && node == 0) a.alpha_s[e] = am;
+    } else {
+        blend = a.alpha != nullptr;
+        alpha = (blend && valid) ? real(a.alpha[es]) : real(0);
+    }
 
-    // face membership of this node
     bool onface[DIM];
     int side[DIM];
 #pragma unroll
@@ -148,33 +210,25 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
         side[d] = (pd[d] == N) ? 1 : 0;
     }
 
-    real Z[MAXS][M];     // Z[k] = sum_{j<k} a_kj R^(j), for the stages still to come
-#pragma unroll
-    for (int k = 0; k < MAXS; ++k)
-#pragma unroll
-        for (int v = 0; v < M; ++v) Z[k][v] = real(0);
+    real Z[S][M];     // Z[k] = sum_{j<k} a_kj R^(j)
     real V[M], U[M], F[DIM][M], Fnc[DIM][M], Lint[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) {
         V[v] = real(0); U[v] = real(0); Lint[v] = real(0);
 #pragma unroll
+        for (int k = 0; k < S; ++k) Z[k][v] = real(0);
+#pragma unroll
         for (int d = 0; d < DIM; ++d) { F[d][v] = real(0); Fnc[d][v] = real(0); }
     }
 
-    for (int i = 0; i < t.stages; ++i) {
-        // stage state
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
         real us[M];
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-            real z = real(0);
-#pragma unroll
-            for (int k = 0; k < MAXS; ++k)
-                if (k == i) z = Z[k][v];
-            us[v] = un[v] - rdt * z;
-        }
+        for (int v = 0; v < M; ++v) us[v] = (i == 0) ? un[v] : un[v] - rdt * Z[i][v];
         real nd[NF];
         Phys::node(us, nd, ctx);
-        if (i > 0) __syncthreads();       // previous stage finished reading LDS
+        if (i > 0) __syncthreads();       // the previous stage has finished reading LDS
 #pragma unroll
         for (int f = 0; f < NF; ++f) lds[f][tid] = nd[f];
         __syncthreads();
@@ -185,12 +239,14 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
         const real bi = real(t.b[i]);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            // off-diagonal pairs along the d-line
+            // directly evaluated rotations
 #pragma unroll
             for (int k = 1; k <= N; ++k) {
+                const bool direct = !SYM || k <= NPRIM || k == KSELF;
+                if (!direct) continue;
                 int qd = pd[d] + k;
                 if (qd >= n1) qd -= n1;
-                const int q = (DIM == 1) ? qd : (d == 0 ? pd[1] * n1 + qd : qd * n1 + pd[0]);
+                const int q = line_node<N, DIM>(pd, d, qd);
                 real ndq[NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) ndq[f] = lds[f][base + q];
@@ -198,6 +254,12 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
                 Phys::pair(d, nd, ndq, fs, ctx);
 #pragma unroll
                 for (int v = 0; v < M; ++v) R[v] += Dk[d][k - 1] * fs[v];
+                if constexpr (SYM) {
+                    if (k <= NPRIM) {
+#pragma unroll
+                        for (int v = 0; v < M; ++v) xch[(d * NPRIM + (k - 1)) * M + v][tid] = fs[v];
+                    }
+                }
             }
             // diagonal term 2 D_pp f_d(u_p) (non-zero only at the two ends of
             // the line) and the face traces in the same branch
@@ -221,7 +283,7 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
                 real gB = real(0), gpsi = real(0);
 #pragma unroll
                 for (int q = 0; q < n1; ++q) {
-                    const int qq = (d == 0 ? pd[1] * n1 + q : q * n1 + pd[0]);
+                    const int qq = line_node<N, DIM>(pd, d, q);
                     gB += Dn[d][q] * lds[5 + d][base + qq];
                     gpsi += Dn[d][q] * lds[8][base + qq];
                 }
@@ -232,18 +294,16 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
             }
             // first-order subcell fluxes of the blending limiter, from u^n = u^(1)
             if (i == 0 && blend && alpha > real(0)) {
-                real fr[M], fl[M];
+                real fr[M], fl[M], fp[M];
 #pragma unroll
                 for (int v = 0; v < M; ++v) { fr[v] = real(0); fl[v] = real(0); }
-                real fp[M];
                 Phys::phys(d, nd, fp, ctx);
-                const real *up = un;
                 const real lp = Phys::speed(d, nd, ctx);
 #pragma unroll
                 for (int sgn = 0; sgn < 2; ++sgn) {
                     const int qd = sgn ? pd[d] + 1 : pd[d] - 1;
                     if (qd < 0 || qd > N) continue;
-                    const int q = (DIM == 1) ? qd : (d == 0 ? pd[1] * n1 + qd : qd * n1 + pd[0]);
+                    const int q = line_node<N, DIM>(pd, d, qd);
                     real ndq[NF], fq[M], uq[M];
 #pragma unroll
                     for (int f = 0; f < NF; ++f) ndq[f] = lds[f][base + q];
@@ -252,22 +312,35 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
                     const real lam = dmax(lp, Phys::speed(d, ndq, ctx));
 #pragma unroll
                     for (int v = 0; v < M; ++v) {
-                        if (sgn) fr[v] = real(0.5) * (fp[v] + fq[v]) - real(0.5) * lam * (uq[v] - up[v]);
-                        else fl[v] = real(0.5) * (fq[v] + fp[v]) - real(0.5) * lam * (up[v] - uq[v]);
+                        if (sgn) fr[v] = real(0.5) * (fp[v] + fq[v]) - real(0.5) * lam * (uq[v] - un[v]);
+                        else fl[v] = real(0.5) * (fq[v] + fp[v]) - real(0.5) * lam * (un[v] - uq[v]);
                     }
                 }
 #pragma unroll
                 for (int v = 0; v < M; ++v) Lint[v] += invw[d] * (fr[v] - fl[v]);
             }
         }
+        if constexpr (SYM) {
+            __syncthreads();
+#pragma unroll
+            for (int d = 0; d < DIM; ++d)
+#pragma unroll
+                for (int k = 1; k <= NPRIM; ++k) {
+                    // mirror rotation n1 - k: the pair (p, p - k) was evaluated by lane p - k
+                    int sd = pd[d] - k;
+                    if (sd < 0) sd += n1;
+                    const int src = base + line_node<N, DIM>(pd, d, sd);
+                    const real c = Dk[d][n1 - k - 1];
+#pragma unroll
+                    for (int v = 0; v < M; ++v) R[v] += c * xch[(d * NPRIM + (k - 1)) * M + v][src];
+                }
+        }
         // stage bookkeeping
 #pragma unroll
-        for (int k = 0; k < MAXS; ++k) {
-            if (k > i && k < t.stages) {
-                const real aki = real(t.A[k][i]);
+        for (int k = i + 1; k < S; ++k) {
+            const real aki = real(t.A[k][i]);
 #pragma unroll
-                for (int v = 0; v < M; ++v) Z[k][v] += aki * R[v];
-            }
+            for (int v = 0; v < M; ++v) Z[k][v] += aki * R[v];
         }
 #pragma unroll
         for (int v = 0; v < M; ++v) {
@@ -294,25 +367,103 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
 #pragma unroll
     for (int v = 0; v < M; ++v) uout[((long)v * E + e) * NP + node] = res[v];
 
-    // traces
+    // traces [face][c][e][k], c < 2M: U then F
     real *tr = (real *)a.traces;
-    const int nf = DIM == 2 ? n1 : 1;
+    constexpr int nf = DIM == 2 ? n1 : 1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         if (!onface[d]) continue;
         const int face = 2 * d + side[d];
         const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
-        real *tb = tr + ((long)face * 3 * M * E + e) * nf + kk;
+        real *tb = tr + ((long)face * 2 * M * E + e) * nf + kk;
 #pragma unroll
         for (int v = 0; v < M; ++v) {
             tb[((long)v * E) * nf] = U[v];
             tb[((long)(M + v) * E) * nf] = F[d][v];
-            tb[((long)(2 * M + v) * E) * nf] = un[v];
         }
     }
 }
 
+// ---------------------------------------------------------------- K8 helper: modal indicator
+// Blending coefficient of one element from eps = rho*p at its nodes, one lane
+// per node: modal coefficients in the orthonormal Legendre basis, energy in
+// the highest modes, logistic map (Hennemann-Gassner form), clipping at
+// alpha_min and cap at alpha_max.  Every lane of the workgroup must call it.
+template <int DIM, int N>
+__device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le, int node, long e, bool valid,
+                                                double eps_node, double *eps, double (*en)[BLOCK], double *alpha_raw)
+{
+    constexpr int n1 = N + 1;
+    constexpr int NP = DIM == 2 ? n1 * n1 : n1;
+    eps[tid] = eps_node;
+    __syncthreads();
+    const int mk = node % n1, ml = DIM == 2 ? node / n1 : 0;
+    double rk[n1], rl[n1];
+#pragma unroll
+    for (int c = 0; c < n1; ++c) {
+        double x = 0.0, y = 0.0;
+#pragma unroll
+        for (int r = 0; r < n1; ++r) {
+            if (mk == r) x = t.Vinv[r][c];
+            if (ml == r) y = t.Vinv[r][c];
+        }
+        rk[c] = x;
+        rl[c] = y;
+    }
+    double m = 0.0;
+    if constexpr (DIM == 1) {
+#pragma unroll
+        for (int i = 0; i < n1; ++i) m += rk[i] * eps[le * NP + i];
+    } else {
+#pragma unroll
+        for (int j = 0; j < n1; ++j) {
+            double sj = 0.0;
+#pragma unroll
+            for (int i = 0; i < n1; ++i) sj += rk[i] * eps[le * NP + j * n1 + i];
+            m += rl[j] * sj;
+        }
+    }
+    const double e2 = m * m;
+    en[0][tid] = e2;
+    en[1][tid] = (mk <= N - 1 && ml <= N - 1) ? e2 : 0.0;
+    en[2][tid] = (mk <= N - 2 && ml <= N - 2) ? e2 : 0.0;
+    __syncthreads();
+    if (valid && node == 0) {
+        double tot = 0.0, c1 = 0.0, c2 = 0.0;
+        for (int p = 0; p < NP; ++p) {
+            tot += en[0][le * NP + p];
+            c1 += en[1][le * NP + p];
+            c2 += en[2][le * NP + p];
+        }
+        const double E1 = (tot - c1) / tot, E2 = (c1 - c2) / c1;
+        const double En = E1 > E2 ? E1 : E2;
+        double al = 1.0 / (1.0 + exp(-(t.ind_sharpness / t.ind_threshold) * (En - t.ind_threshold)));
+        if (al < t.alpha_min) al = 0.0;
+        if (al > 1.0 - t.alpha_min) al = 1.0;
+        if (al > t.alpha_max) al = t.alpha_max;
+        alpha_raw[e] = al;
+    }
+}
+
+// Workgroup maximum of v (all lanes call) into partials[blockIdx.x]; a
+// one-workgroup kernel finishes the reduction after the grid has drained.
+__device__ __forceinline__ void block_max_lanes(double v, double *red, double *partials)
+{
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+        __syncthreads();
+    }
+    if (tid == 0) partials[blockIdx.x] = red[0];
+}
+
 // ---------------------------------------------------------------- K3: interface + final update
+// One lane per node; the face-node lanes apply the interface corrections.
+// u^n at the face nodes of both sides is read from the state the step
+// started from.  In the pipelined step every lane then holds u^{n+1} of its
+// node and the workgroup computes the CFL maximum and the raw indicator.
 template <typename real, int EQ, int DIM, int N, int FLUX>
 __global__ void __launch_bounds__(BLOCK) k_interface(const Tables t, const StepPtrs a)
 {
@@ -323,88 +474,129 @@ __global__ void __launch_bounds__(BLOCK) k_interface(const Tables t, const StepP
     constexpr int M = Phys::M;
     constexpr int NF = Phys::NF;
     const int tid = threadIdx.x;
-    const int le = tid / NP;
+    int le = tid / NP;
     const int node = tid - le * NP;
     const long e = (long)blockIdx.x * EPB + le;
-    if (le >= EPB || e >= t.nelem) return;
+    const bool valid = (le < EPB) && (e < t.nelem);
+    if (le >= EPB) le = 0;
+    const long es = valid ? e : 0;
     const int pd[2] = {node % n1, DIM == 2 ? node / n1 : 0};
-    bool any = false;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) any |= (pd[d] == 0 || pd[d] == N);
-    if (!any) return;
+    const bool tail = a.dt_out != nullptr;
 
     const long E = t.nelem;
-    const int nf = DIM == 2 ? n1 : 1;
+    constexpr int nf = DIM == 2 ? n1 : 1;
     const Ctx<real> ctx = make_ctx<real>(t, a.dt);
     const real rdt = real(a.dt[0]);
     const bool blend = a.alpha != nullptr;
-    const real alpha_e = blend ? real(a.alpha[e]) : real(0);
+    const real alpha_e = blend ? real(a.alpha[es]) : real(0);
     const real *tr = (const real *)a.traces;
+    const real *uin = (const real *)a.u_in;
     real *uo = (real *)a.u_out;
 
-    real u[M];
+    bool face_lane = false;
 #pragma unroll
-    for (int v = 0; v < M; ++v) u[v] = uo[((long)v * E + e) * NP + node];
+    for (int d = 0; d < DIM; ++d) face_lane |= (pd[d] == 0 || pd[d] == N);
+    face_lane &= valid;
 
+    real u[M];
+    if (face_lane || (tail && valid)) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        if (!(pd[d] == 0 || pd[d] == N)) continue;
-        const int side = pd[d] == N ? 1 : 0;
-        const long en = neighbour(t, e, d, side);
-        const int face = 2 * d + side, nface = 2 * d + 1 - side;
-        const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
-        const real *to = tr + ((long)face * 3 * M * E + e) * nf + kk;
-        const real *tn = tr + ((long)nface * 3 * M * E + en) * nf + kk;
-        real Uo[M], Fo[M], uno[M], Un[M], Fn[M], unn[M];
+        for (int v = 0; v < M; ++v) u[v] = uo[((long)v * E + e) * NP + node];
+    } else {
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-            Uo[v] = to[((long)v * E) * nf];
-            Fo[v] = to[((long)(M + v) * E) * nf];
-            uno[v] = to[((long)(2 * M + v) * E) * nf];
-            Un[v] = tn[((long)v * E) * nf];
-            Fn[v] = tn[((long)(M + v) * E) * nf];
-            unn[v] = tn[((long)(2 * M + v) * E) * nf];
-        }
-        real ndo[NF], ndn[NF];
+        for (int v = 0; v < M; ++v) u[v] = real(v == 0 ? 1 : 0);
+    }
+    if (face_lane) {
+        real uno[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) uno[v] = uin[((long)v * E + e) * NP + node];
+        real ndo[NF];
         Phys::node_basic(uno, ndo, ctx);
-        Phys::node_basic(unn, ndn, ctx);
-        const real lam = dmax(Phys::speed(d, ndo, ctx), Phys::speed(d, ndn, ctx));
-        // left (-) / right (+) of the interface
-        const real *UL = side ? Uo : Un, *UR = side ? Un : Uo;
-        const real *FL = side ? Fo : Fn, *FR = side ? Fn : Fo;
-        real Fs[M];
+        const Nbrs nb = neighbours(t, e);
 #pragma unroll
-        for (int v = 0; v < M; ++v) Fs[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * lam * (UR[v] - UL[v]);
-        if (blend) {
-            const real aface = real(0.5) * (alpha_e + real(a.alpha[en]));
-            if (aface > real(0)) {
-                real fo[M], fn[M];
-                Phys::phys(d, ndo, fo, ctx);
-                Phys::phys(d, ndn, fn, ctx);
-                const real *fL = side ? fo : fn, *fR = side ? fn : fo;
-                const real *uL = side ? uno : unn, *uR = side ? unn : uno;
+        for (int d = 0; d < DIM; ++d) {
+            if (!(pd[d] == 0 || pd[d] == N)) continue;
+            const int side = pd[d] == N ? 1 : 0;
+            const long en = nb.n[d][side];
+            const int face = 2 * d + side, nface = 2 * d + 1 - side;
+            const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
+            int qd[2] = {pd[0], pd[1]};
+            qd[d] = N - pd[d];                      // the neighbour's node facing this one
+            const int nnode = DIM == 1 ? qd[0] : qd[1] * n1 + qd[0];
+            const real *to = tr + ((long)face * 2 * M * E + e) * nf + kk;
+            const real *tn = tr + ((long)nface * 2 * M * E + en) * nf + kk;
+            real Uo[M], Fo[M], Un[M], Fn[M], unn[M];
 #pragma unroll
-                for (int v = 0; v < M; ++v) {
-                    const real flo = real(0.5) * (fL[v] + fR[v]) - real(0.5) * lam * (uR[v] - uL[v]);
-                    Fs[v] = (real(1) - aface) * Fs[v] + aface * flo;
+            for (int v = 0; v < M; ++v) {
+                Uo[v] = to[((long)v * E) * nf];
+                Fo[v] = to[((long)(M + v) * E) * nf];
+                Un[v] = tn[((long)v * E) * nf];
+                Fn[v] = tn[((long)(M + v) * E) * nf];
+                unn[v] = uin[((long)v * E + en) * NP + nnode];
+            }
+            real ndn[NF];
+            Phys::node_basic(unn, ndn, ctx);
+            const real lam = dmax(Phys::speed(d, ndo, ctx), Phys::speed(d, ndn, ctx));
+            const real *UL = side ? Uo : Un, *UR = side ? Un : Uo;
+            const real *FL = side ? Fo : Fn, *FR = side ? Fn : Fo;
+            real Fs[M];
+#pragma unroll
+            for (int v = 0; v < M; ++v) Fs[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * lam * (UR[v] - UL[v]);
+            if (blend) {
+                const real aface = real(0.5) * (alpha_e + real(a.alpha[en]));
+                if (aface > real(0)) {
+                    real fo[M], fn[M];
+                    Phys::phys(d, ndo, fo, ctx);
+                    Phys::phys(d, ndn, fn, ctx);
+                    const real *fL = side ? fo : fn, *fR = side ? fn : fo;
+                    const real *uL = side ? uno : unn, *uR = side ? unn : uno;
+#pragma unroll
+                    for (int v = 0; v < M; ++v) {
+                        const real flo = real(0.5) * (fL[v] + fR[v]) - real(0.5) * lam * (uR[v] - uL[v]);
+                        Fs[v] = (real(1) - aface) * Fs[v] + aface * flo;
+                    }
                 }
             }
+            real jump[M];
+#pragma unroll
+            for (int v = 0; v < M; ++v) jump[v] = Fs[v] - (real(1) - alpha_e) * Fo[v];
+            if constexpr (EQ == EQ_MHD) {
+                real o[M];
+                MhdP<real, FLUX>::btimes(d, ndo, real(0.5) * (UL[5 + d] + UR[5 + d]), real(0.5) * (UL[8] + UR[8]), o);
+#pragma unroll
+                for (int v = 0; v < M; ++v) jump[v] += o[v];
+            }
+            const real coef = rdt * real(t.invw_dx[d][0]);
+#pragma unroll
+            for (int v = 0; v < M; ++v) u[v] += side ? -coef * jump[v] : coef * jump[v];
         }
-        real jump[M];
 #pragma unroll
-        for (int v = 0; v < M; ++v) jump[v] = Fs[v] - (real(1) - alpha_e) * Fo[v];
-        if constexpr (EQ == EQ_MHD) {
-            real o[M];
-            MhdP<real, FLUX>::btimes(d, ndo, real(0.5) * (UL[5 + d] + UR[5 + d]), real(0.5) * (UL[8] + UR[8]), o);
-#pragma unroll
-            for (int v = 0; v < M; ++v) jump[v] += o[v];
-        }
-        const real coef = rdt * real(t.invdx[d] / t.w[0]);
-#pragma unroll
-        for (int v = 0; v < M; ++v) u[v] += side ? -coef * jump[v] : coef * jump[v];
+        for (int v = 0; v < M; ++v) uo[((long)v * E + e) * NP + node] = u[v];
     }
+    if (!tail) return;
+
+    // pipelined tail: CFL maximum and raw indicator of u^{n+1}
+    __shared__ double red[BLOCK];
+    real nd[NF];
+    Phys::node_basic(u, nd, ctx);
+    double sp = 0.0;
+    if (valid) {
 #pragma unroll
-    for (int v = 0; v < M; ++v) uo[((long)v * E + e) * NP + node] = u[v];
+        for (int d = 0; d < DIM; ++d) {
+            if constexpr (EQ == EQ_MHD) sp = fmax(sp, (double)MhdP<real, FLUX>::fast(d, nd, ctx));
+            else sp += (double)Phys::speed(d, nd, ctx) * t.invdx[d];
+        }
+    }
+    if constexpr (EQ == EQ_EULER) {
+        if (a.alpha_raw_out != nullptr) {
+            __shared__ double eps[BLOCK];
+            __shared__ double en[3][BLOCK];
+            real rho, v[DIM], p, Ev;
+            Phys::prim(nd, rho, v, p, Ev, ctx);
+            indicator_lanes<DIM, N>(t, tid, le, node, e, valid, (double)rho * (double)p, eps, en, a.alpha_raw_out);
+        }
+    }
+    block_max_lanes(sp, red, a.partials);
 }
 
 // ---------------------------------------------------------------- K1: time step
@@ -442,7 +634,8 @@ __global__ void __launch_bounds__(BLOCK) k_dt_partial(const Tables t, const void
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-static __global__ void __launch_bounds__(BLOCK) k_dt_final(const Tables t, const double *partials, int nparts, int is_mhd, double *dt)
+static __global__ void __launch_bounds__(BLOCK) k_dt_final(const Tables t, const double *partials, int nparts, int is_mhd,
+                                                            double *dt)
 {
     __shared__ double red[BLOCK];
     double mx = 0.0;
@@ -494,54 +687,7 @@ __global__ void __launch_bounds__(BLOCK) k_indicator(const Tables t, const void 
 #pragma unroll
     for (int k = 0; k < DIM; ++k) ke += us[1 + k] * us[1 + k];
     const double p = (t.gamma - 1.0) * (us[DIM + 1] - 0.5 * ke / us[0]);
-    eps[tid] = us[0] * p;
-    __syncthreads();
-    // modal coefficient m_kl of this lane's mode (k, l) = (i, j)
-    const int mk = node % n1, ml = DIM == 2 ? node / n1 : 0;
-    double rk[n1], rl[n1];
-#pragma unroll
-    for (int c = 0; c < n1; ++c) {
-        double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int r = 0; r < n1; ++r) {
-            if (mk == r) a = t.Vinv[r][c];
-            if (ml == r) b = t.Vinv[r][c];
-        }
-        rk[c] = a;
-        rl[c] = b;
-    }
-    double m = 0.0;
-    if (DIM == 1) {
-#pragma unroll
-        for (int i = 0; i < n1; ++i) m += rk[i] * eps[le * NP + i];
-    } else {
-#pragma unroll
-        for (int j = 0; j < n1; ++j) {
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < n1; ++i) s += rk[i] * eps[le * NP + j * n1 + i];
-            m += rl[j] * s;
-        }
-    }
-    const double e2 = m * m;
-    en[0][tid] = e2;
-    en[1][tid] = (mk <= N - 1 && ml <= N - 1) ? e2 : 0.0;
-    en[2][tid] = (mk <= N - 2 && ml <= N - 2) ? e2 : 0.0;
-    __syncthreads();
-    if (!valid || node != 0) return;
-    double tot = 0.0, c1 = 0.0, c2 = 0.0;
-    for (int p = 0; p < NP; ++p) {
-        tot += en[0][le * NP + p];
-        c1 += en[1][le * NP + p];
-        c2 += en[2][le * NP + p];
-    }
-    const double E1 = (tot - c1) / tot, E2 = (c1 - c2) / c1;
-    const double En = E1 > E2 ? E1 : E2;
-    double al = 1.0 / (1.0 + exp(-(t.ind_sharpness / t.ind_threshold) * (En - t.ind_threshold)));
-    if (al < t.alpha_min) al = 0.0;
-    if (al > 1.0 - t.alpha_min) al = 1.0;
-    if (al > t.alpha_max) al = t.alpha_max;
-    alpha_raw[e] = al;
+    indicator_lanes<DIM, N>(t, tid, le, node, e, valid, us[0] * p, eps, en, alpha_raw);
 }
 
 static __global__ void __launch_bounds__(BLOCK) k_smooth(const Tables t, const double *alpha_raw, double *alpha)
@@ -642,7 +788,15 @@ hipError_t launch_local(const Tables &t, const StepPtrs &p, hipStream_t s)
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     constexpr int EPB = BLOCK / NP;
     const int grid = (t.nelem + EPB - 1) / EPB;
-    hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(BLOCK), 0, s, t, p);
+    switch (t.stages) {
+    case 1: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 1>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
+    case 2: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 2>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
+    case 3: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 3>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
+    case 4: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
+    case 5: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 5>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
+    case 6: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -653,6 +807,9 @@ hipError_t launch_interface(const Tables &t, const StepPtrs &p, hipStream_t s)
     constexpr int EPB = BLOCK / NP;
     const int grid = (t.nelem + EPB - 1) / EPB;
     hipLaunchKernelGGL((k_interface<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(BLOCK), 0, s, t, p);
+    if (p.dt_out != nullptr)
+        hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(BLOCK), 0, s, t, (const double *)p.partials, grid,
+                           EQ == EQ_MHD ? 1 : 0, p.dt_out);
     return hipGetLastError();
 }
 

@@ -74,7 +74,8 @@ __device__ __forceinline__ real inv_lnmean(real x, real y, real lx, real ly)
 // ---------------------------------------------------------------- Euler
 // u = (rho, rho v_1 [, rho v_2], E), p = (gamma - 1)(E - rho |v|^2 / 2).
 // Fields: 0 rho, 1..DIM v, DIM+1 p, then per flux
-//   KG:      DIM+2 e = E/rho
+//   KG:      DIM+2 e = E/rho; all KG fields are stored halved, so that the
+//            arithmetic means of the flux are plain sums
 //   central: DIM+2 E
 //   Ranocha: DIM+2 ln rho, DIM+3 beta = rho/p, DIM+4 ln beta
 template <typename real, int DIM, int FLUX>
@@ -82,78 +83,88 @@ struct EulerP {
     static constexpr int M = DIM + 2;
     static constexpr int NF = (FLUX == VOL_RANOCHA) ? DIM + 5 : DIM + 3;
     static constexpr int P = DIM + 1;
+    static constexpr bool HALF = (FLUX == VOL_KG);
 
-    __device__ __forceinline__ static void node(const real *u, real *nd, const Ctx<real> &c)
+    // fields from the conserved state; with logs = false the logarithms of
+    // the Ranocha flux are skipped (enough for phys, speed, cons)
+    template <bool LOGS = true>
+    __device__ __forceinline__ static void fields(const real *u, real *nd, const Ctx<real> &c)
     {
         const real rho = u[0], irho = real(1) / rho;
-        real ke = real(0);
+        real ke = real(0), v[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            nd[1 + k] = u[1 + k] * irho;
-            ke += u[1 + k] * nd[1 + k];
+            v[k] = u[1 + k] * irho;
+            ke += u[1 + k] * v[k];
         }
         const real p = c.gm1 * (u[DIM + 1] - real(0.5) * ke);
-        nd[0] = rho;
-        nd[P] = p;
-        if constexpr (FLUX == VOL_KG) {
-            nd[DIM + 2] = u[DIM + 1] * irho;
-        } else if constexpr (FLUX == VOL_CENTRAL) {
-            nd[DIM + 2] = u[DIM + 1];
+        if constexpr (HALF) {
+            const real h = real(0.5);
+            nd[0] = h * rho;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) nd[1 + k] = h * v[k];
+            nd[P] = h * p;
+            nd[DIM + 2] = h * (u[DIM + 1] * irho);
         } else {
-            const real beta = rho / p;
-            nd[DIM + 2] = dlog(rho);
-            nd[DIM + 3] = beta;
-            nd[DIM + 4] = dlog(beta);
+            nd[0] = rho;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) nd[1 + k] = v[k];
+            nd[P] = p;
+            if constexpr (FLUX == VOL_CENTRAL) {
+                nd[DIM + 2] = u[DIM + 1];
+            } else if constexpr (LOGS) {
+                const real beta = rho / p;
+                nd[DIM + 2] = dlog(rho);
+                nd[DIM + 3] = beta;
+                nd[DIM + 4] = dlog(beta);
+            }
         }
     }
+    __device__ __forceinline__ static void node(const real *u, real *nd, const Ctx<real> &c) { fields<true>(u, nd, c); }
+    __device__ __forceinline__ static void node_basic(const real *u, real *nd, const Ctx<real> &c) { fields<false>(u, nd, c); }
 
-    // the fields that phys(), speed() and cons() read (no logarithms)
-    __device__ __forceinline__ static void node_basic(const real *u, real *nd, const Ctx<real> &c)
+    // full primitive values from the fields
+    __device__ __forceinline__ static void prim(const real *nd, real &rho, real *v, real &p, real &E, const Ctx<real> &c)
     {
-        const real rho = u[0], irho = real(1) / rho;
+        const real s = HALF ? real(2) : real(1);
+        rho = s * nd[0];
         real ke = real(0);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            nd[1 + k] = u[1 + k] * irho;
-            ke += u[1 + k] * nd[1 + k];
+            v[k] = s * nd[1 + k];
+            ke += v[k] * v[k];
         }
-        nd[0] = rho;
-        nd[P] = c.gm1 * (u[DIM + 1] - real(0.5) * ke);
-        if constexpr (FLUX == VOL_KG) nd[DIM + 2] = u[DIM + 1] * irho;
-        else if constexpr (FLUX == VOL_CENTRAL) nd[DIM + 2] = u[DIM + 1];
-    }
-
-    __device__ __forceinline__ static real energy(const real *nd, const Ctx<real> &c)
-    {
-        if constexpr (FLUX == VOL_KG) return nd[0] * nd[DIM + 2];
-        if constexpr (FLUX == VOL_CENTRAL) return nd[DIM + 2];
-        real ke = real(0);
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) ke += nd[1 + k] * nd[1 + k];
-        return nd[P] * c.inv_gm1 + real(0.5) * nd[0] * ke;
+        p = s * nd[P];
+        if constexpr (HALF) E = rho * (s * nd[DIM + 2]);
+        else if constexpr (FLUX == VOL_CENTRAL) E = nd[DIM + 2];
+        else E = p * c.inv_gm1 + real(0.5) * rho * ke;
     }
 
     __device__ __forceinline__ static void cons(const real *nd, real *u, const Ctx<real> &c)
     {
-        u[0] = nd[0];
+        real rho, v[DIM], p, E;
+        prim(nd, rho, v, p, E, c);
+        u[0] = rho;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) u[1 + k] = nd[0] * nd[1 + k];
-        u[DIM + 1] = energy(nd, c);
+        for (int k = 0; k < DIM; ++k) u[1 + k] = rho * v[k];
+        u[DIM + 1] = E;
     }
 
-    // physical flux from the fields (E recomputed for KG/Ranocha)
     __device__ __forceinline__ static void phys(int d, const real *nd, real *f, const Ctx<real> &c)
     {
-        const real vd = nd[1 + d], m = nd[0] * vd;
+        real rho, v[DIM], p, E;
+        prim(nd, rho, v, p, E, c);
+        const real m = rho * v[d];
         f[0] = m;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) f[1 + k] = m * nd[1 + k] + (k == d ? nd[P] : real(0));
-        f[DIM + 1] = (energy(nd, c) + nd[P]) * vd;
+        for (int k = 0; k < DIM; ++k) f[1 + k] = m * v[k] + (k == d ? p : real(0));
+        f[DIM + 1] = (E + p) * v[d];
     }
 
     __device__ __forceinline__ static real speed(int d, const real *nd, const Ctx<real> &c)
     {
-        return dabs(nd[1 + d]) + dsqrt(c.gamma * nd[P] / nd[0]);
+        // (gamma p / rho) is the same with halved p and rho
+        return dabs((HALF ? real(2) : real(1)) * nd[1 + d]) + dsqrt(c.gamma * nd[P] / nd[0]);
     }
 
     __device__ __forceinline__ static void pair(int d, const real *a, const real *b, real *f, const Ctx<real> &c)
@@ -165,14 +176,15 @@ struct EulerP {
 #pragma unroll
             for (int v = 0; v < M; ++v) f[v] = real(0.5) * (fa[v] + fb[v]);
         } else if constexpr (FLUX == VOL_KG) {
-            const real rho = real(0.5) * (a[0] + b[0]);
-            const real vd = real(0.5) * (a[1 + d] + b[1 + d]);
-            const real p = real(0.5) * (a[P] + b[P]);
-            const real e = real(0.5) * (a[DIM + 2] + b[DIM + 2]);
+            // fields are halved: every arithmetic mean is a sum
+            const real rho = a[0] + b[0];
+            const real vd = a[1 + d] + b[1 + d];
+            const real p = a[P] + b[P];
+            const real e = a[DIM + 2] + b[DIM + 2];
             const real m = rho * vd;
             f[0] = m;
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) f[1 + k] = m * (real(0.5) * (a[1 + k] + b[1 + k])) + (k == d ? p : real(0));
+            for (int k = 0; k < DIM; ++k) f[1 + k] = (k == d ? m * vd + p : m * (a[1 + k] + b[1 + k]));
             f[DIM + 1] = (rho * e + p) * vd;
         } else {
             const real rho_ln = lnmean(a[0], b[0], a[DIM + 2], b[DIM + 2]);
@@ -185,7 +197,7 @@ struct EulerP {
             f[0] = m;
 #pragma unroll
             for (int k = 0; k < DIM; ++k)
-                f[1 + k] = m * (real(0.5) * (a[1 + k] + b[1 + k])) + (k == d ? real(0.5) * (a[P] + b[P]) : real(0));
+                f[1 + k] = (k == d) ? m * vd + real(0.5) * (a[P] + b[P]) : m * (real(0.5) * (a[1 + k] + b[1 + k]));
             f[DIM + 1] = m * (ibeta_ln * c.inv_gm1 + real(0.5) * vv) + real(0.5) * (a[P] * b[1 + d] + b[P] * a[1 + d]);
         }
     }
