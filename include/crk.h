@@ -177,6 +177,43 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
  * non-finite or has rho <= 0 or p <= 0 (-1 if none).  Needs the workspace. */
 crk_status crk_diagnostics(crk_solver *s, const void *u, double *out_dev, crk_stream stream);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent periodic 2D Euler meshes (degree 3 with classical RK4,
+ * degree 4 with Butcher's RK5, one precision, Kennedy-Gruber or Ranocha
+ * volume flux, no limiter) advanced together by pipelined steps.  The
+ * element tiles of all problems form one work list walked by persistent
+ * kernels: one launch per phase, whatever the mix of degrees; each problem
+ * has its own CFL time step.  Each problem i occupies the values
+ * [offsets[i], offsets[i+1]) of a state buffer, laid out as u[v][e][node]
+ * of that problem. */
+typedef struct crk_batch crk_batch;
+typedef struct {
+    int block;          /* lanes per workgroup: 64, 128 or 256 (0: 256)           */
+    int grid_per_cu;    /* persistent workgroups per compute unit; 0: one per tile */
+} crk_batch_tuning;
+/* meshes[nprob]; scheme->A and ->b must be NULL.  tuning may be NULL. */
+crk_status crk_batch_create(const crk_mesh_desc *meshes, int nprob, const crk_scheme_desc *scheme,
+                            const crk_batch_tuning *tuning, crk_batch **out);
+crk_status crk_batch_destroy(crk_batch *b);
+/* offsets[nprob+1] (values), degrees[nprob], bytes of one state buffer, of
+ * the workspace, and the number of work items; any pointer may be NULL. */
+crk_status crk_batch_layout(const crk_batch *b, int64_t *offsets, int *degrees, size_t *state_bytes,
+                            size_t *workspace_bytes, int64_t *ntiles);
+/* Bind the two state buffers u0, u1, the time steps dt_dev[2*nprob]
+ * (dt_dev[2i] = dt of problem i) and the workspace; uploads the work list
+ * (synchronises `stream`). */
+crk_status crk_batch_bind(crk_batch *b, void *u0, void *u1, double *dt_dev, void *workspace, size_t ws_bytes,
+                          crk_stream stream);
+/* dt of every problem from state src (0: u0, 1: u1). */
+crk_status crk_batch_prepare(crk_batch *b, int src, crk_stream stream);
+/* One pipelined step from state src into the other buffer (phases as for
+ * crk_advance); leaves the dt of the new states in dt_dev. */
+crk_status crk_batch_advance(crk_batch *b, int src, int phases, crk_stream stream);
+/* Capture two steps u0 -> u1 -> u0 into a HIP graph (stream must not be the
+ * default stream), and replay it. */
+crk_status crk_batch_graph_capture(crk_batch *b, crk_stream stream);
+crk_status crk_batch_graph_launch(crk_batch *b, crk_stream stream);
+
 /* Message of the last error on this thread ("" if none). */
 const char *crk_last_error(void);
 

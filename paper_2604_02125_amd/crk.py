@@ -224,3 +224,113 @@ class Solver:
         out = torch.empty(self.shape[0] + 5, dtype=torch.float64, device=self.device)
         _check(lib().crk_diagnostics(self._h, _ptr(u), _ptr(out), _stream(stream)), "crk_diagnostics")
         return out
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("block", C.c_int), ("grid_per_cu", C.c_int)]
+
+
+TUNING_PATH = os.path.join(HERE, "tuning.json")
+
+
+def load_tuning(precision: int, volume_flux: int):
+    """Tile shape chosen by the autotuner for (precision, flux), or None."""
+    import json
+    if not os.path.exists(TUNING_PATH):
+        return None
+    with open(TUNING_PATH) as fh:
+        tab = json.load(fh)
+    key = f"{'fp64' if precision == FP64 else 'fp32'}/{ {VOL_KG: 'kg', VOL_RANOCHA: 'ranocha'}.get(volume_flux, '?') }"
+    rec = tab.get("batch", {}).get(key)
+    return None if rec is None else (int(rec["block"]), int(rec["grid_per_cu"]))
+
+
+def _bind_batch_functions(L):
+    st = C.c_int
+    sig = {
+        "crk_batch_create": (st, [C.POINTER(MeshDesc), C.c_int, C.POINTER(SchemeDesc), C.POINTER(BatchTuning),
+                                  C.POINTER(_vp)]),
+        "crk_batch_destroy": (st, [_vp]),
+        "crk_batch_layout": (st, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_size_t),
+                                  C.POINTER(C.c_size_t), C.POINTER(C.c_int64)]),
+        "crk_batch_bind": (st, [_vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]),
+        "crk_batch_prepare": (st, [_vp, C.c_int, _vp]),
+        "crk_batch_advance": (st, [_vp, C.c_int, C.c_int, _vp]),
+        "crk_batch_graph_capture": (st, [_vp, _vp]),
+        "crk_batch_graph_launch": (st, [_vp, _vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+class Batch:
+    """Independent periodic 2D Euler problems on [0,1]^2, problem i with
+    n_i x n_i elements of degree N_i in {3, 4}, advanced together.
+
+    Owns two flat state buffers (u0, u1), the per-problem time steps
+    dt[2*nprob] and the workspace, all bound to the library at creation."""
+
+    def __init__(self, specs, precision=FP64, volume_flux=VOL_RANOCHA, cfl=0.4, gamma=1.4, tuning=None,
+                 device="cuda", stream=None):
+        import numpy as np
+        import torch
+        L = lib()
+        _bind_batch_functions(L)
+        self.device = torch.device(device)
+        self.specs = [(int(n), int(N)) for n, N in specs]
+        self.nprob = len(self.specs)
+        meshes = (MeshDesc * self.nprob)()
+        for i, (n, N) in enumerate(self.specs):
+            meshes[i] = MeshDesc(2, n, n, 0.0, 1.0, 0.0, 1.0, N, CRK_EULER, gamma, precision)
+        sc = SchemeDesc()
+        sc.volume_flux, sc.cfl, sc.limiter = volume_flux, cfl, LIM_NONE
+        if tuning is None:
+            tuning = load_tuning(precision, volume_flux)
+        tn = BatchTuning(*(tuning if tuning is not None else (256, 4)))
+        self.tuning = (tn.block, tn.grid_per_cu)
+        h = _vp()
+        _check(L.crk_batch_create(meshes, self.nprob, C.byref(sc), C.byref(tn), C.byref(h)), "crk_batch_create")
+        self._h = h
+        offs = (C.c_int64 * (self.nprob + 1))()
+        degs = (C.c_int * self.nprob)()
+        sb, wb, nt = C.c_size_t(), C.c_size_t(), C.c_int64()
+        _check(L.crk_batch_layout(h, offs, degs, C.byref(sb), C.byref(wb), C.byref(nt)), "crk_batch_layout")
+        self.offsets = np.array(offs[:], dtype=np.int64)
+        self.ntiles = nt.value
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        n = int(self.offsets[-1])
+        self.u = [torch.zeros(n, dtype=self.dtype, device=self.device) for _ in range(2)]
+        self.dt = torch.zeros(2 * self.nprob, dtype=torch.float64, device=self.device)
+        self.workspace = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        _check(L.crk_batch_bind(h, _ptr(self.u[0]), _ptr(self.u[1]), _ptr(self.dt), _ptr(self.workspace),
+                                wb.value, C.c_void_p(self.stream.cuda_stream)), "crk_batch_bind")
+        self.ndof = sum(n * n * (N + 1) ** 2 for n, N in self.specs)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.crk_batch_destroy(h)
+            self._h = None
+
+    def view(self, buf: int, i: int):
+        """State of problem i in buffer buf (0/1) as a [v, e, node] view."""
+        n, N = self.specs[i]
+        return self.u[buf][self.offsets[i]:self.offsets[i + 1]].view(4, n * n, (N + 1) ** 2)
+
+    def _s(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def prepare(self, src=0):
+        _check(lib().crk_batch_prepare(self._h, src, self._s()), "crk_batch_prepare")
+
+    def advance(self, src, phases=PHASE_LOCAL | PHASE_INTERFACE):
+        _check(lib().crk_batch_advance(self._h, src, phases, self._s()), "crk_batch_advance")
+
+    def capture_graph(self):
+        _check(lib().crk_batch_graph_capture(self._h, self._s()), "crk_batch_graph_capture")
+
+    def launch_graph(self):
+        _check(lib().crk_batch_graph_launch(self._h, self._s()), "crk_batch_graph_launch")

@@ -158,10 +158,21 @@ crk_status crk_reference_element(int N, double *xi, double *w, double *D)
     return CRK_OK;
 }
 
-crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_solver **out)
+} // extern "C"
+
+namespace crk {
+
+const char *set_error(crk_status st, const char *msg)
 {
-    if (!m || !sc || !out) return fail(CRK_ERR_ARG, "null argument");
-    *out = nullptr;
+    (void)st;
+    g_err = msg;
+    return g_err.c_str();
+}
+
+// Validate a mesh + scheme description and build the kernel tables.
+crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables *tp)
+{
+    if (!m || !sc || !tp) return fail(CRK_ERR_ARG, "null argument");
     if (m->dim != 1 && m->dim != 2) return fail(CRK_ERR_ARG, "dim must be 1 or 2");
     if (m->nx < 1 || (m->dim == 2 && m->ny < 1)) return fail(CRK_ERR_ARG, "element counts must be positive");
     if (m->degree < 1 || m->degree > MAXN) return fail(CRK_ERR_UNSUPPORTED, "degree must be 1..4");
@@ -180,13 +191,7 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     const long nelem = m->dim == 2 ? (long)m->nx * m->ny : m->nx;
     if (nelem * nnode >= (1L << 31)) return fail(CRK_ERR_ARG, "mesh too large");
 
-    crk_solver *s = new (std::nothrow) crk_solver();
-    if (!s) return fail(CRK_ERR_ARG, "out of host memory");
-    s->mesh = *m;
-    s->flux = sc->volume_flux;
-    s->limiter = sc->limiter;
-    s->prec = m->precision;
-    Tables &t = s->t;
+    Tables &t = *tp;
     std::memset(&t, 0, sizeof t);
     t.dim = m->dim;
     t.nx = m->nx;
@@ -201,13 +206,13 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     t.gamma = m->gamma;
     t.cfl = sc->cfl;
     if (sc->A && sc->b) {
-        if (sc->stages < 1 || sc->stages > MAXS) { delete s; return fail(CRK_ERR_UNSUPPORTED, "stages must be 1..6"); }
+        if (sc->stages < 1 || sc->stages > MAXS) return fail(CRK_ERR_UNSUPPORTED, "stages must be 1..6");
         t.stages = sc->stages;
         for (int i = 0; i < t.stages; ++i) {
             t.b[i] = sc->b[i];
             for (int j = 0; j < t.stages; ++j) {
                 const double a = sc->A[i * t.stages + j];
-                if (j >= i && a != 0.0) { delete s; return fail(CRK_ERR_ARG, "A must be strictly lower triangular"); }
+                if (j >= i && a != 0.0) return fail(CRK_ERR_ARG, "A must be strictly lower triangular");
                 t.A[i][j] = a;
             }
         }
@@ -240,7 +245,28 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     t.ind_sharpness = std::log((1.0 - 1e-4) / 1e-4);
     t.alpha_min = sc->alpha_min;
     t.alpha_max = sc->alpha_max;
+    return CRK_OK;
+}
 
+} // namespace crk
+
+extern "C" {
+
+crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_solver **out)
+{
+    if (!m || !sc || !out) return fail(CRK_ERR_ARG, "null argument");
+    *out = nullptr;
+    Tables t;
+    crk_status st = fill_tables(m, sc, &t);
+    if (st) return st;
+    crk_solver *s = new (std::nothrow) crk_solver();
+    if (!s) return fail(CRK_ERR_ARG, "out of host memory");
+    s->mesh = *m;
+    s->flux = sc->volume_flux;
+    s->limiter = sc->limiter;
+    s->prec = m->precision;
+    s->t = t;
+    const long nnode = t.nnode, nelem = t.nelem;
     s->elem_bytes = s->prec == CRK_FP64 ? 8 : 4;
     s->state_bytes = (size_t)t.M * nelem * nnode * s->elem_bytes;
     s->trace_bytes = (size_t)2 * t.dim * 2 * t.M * nelem * t.nface * s->elem_bytes;

@@ -115,26 +115,40 @@ __device__ __forceinline__ int line_node(const int *pd, int d, int qd)
     return (DIM == 1) ? qd : (d == 0 ? pd[1] * n1 + qd : qd * n1 + pd[0]);
 }
 
-template <typename real, int EQ, int DIM, int N, int FLUX, int S>
-__global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs a)
+// LDS slots (of BLK values each) used by the local-stage tile
+template <typename real, int EQ, int DIM, int N, int FLUX>
+struct LocalShape {
+    using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
+    static constexpr int n1 = N + 1;
+    static constexpr bool SYM = (EQ == EQ_EULER) && (N >= 2);
+    static constexpr int NPRIM = SYM ? (n1 - 1) / 2 : 0;           // rotations whose mirror comes from LDS
+    static constexpr int KSELF = (SYM && n1 % 2 == 0) ? n1 / 2 : 0;  // self-mirrored rotation, evaluated directly
+    static constexpr int NX = SYM ? DIM * NPRIM * Phys::M : 0;
+    static constexpr int slots = Phys::NF + NX;
+};
+
+// One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
+// smem holds LocalShape::slots * BLK values.
+template <typename real, int EQ, int DIM, int N, int FLUX, int S, int BLK>
+__device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, long e0, real *smem)
 {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
+    using Shape = LocalShape<real, EQ, DIM, N, FLUX>;
     constexpr int n1 = N + 1;
     constexpr int NP = DIM == 2 ? n1 * n1 : n1;
-    constexpr int EPB = BLOCK / NP;
+    constexpr int EPB = BLK / NP;
     constexpr int M = Phys::M;
     constexpr int NF = Phys::NF;
-    constexpr bool SYM = (EQ == EQ_EULER) && (N >= 2);
-    constexpr int NPRIM = SYM ? (n1 - 1) / 2 : 0;          // rotations whose mirror comes from LDS
-    constexpr int KSELF = (SYM && n1 % 2 == 0) ? n1 / 2 : 0; // self-mirrored rotation, evaluated directly
-    constexpr int NX = SYM ? DIM * NPRIM * M : 1;
-    __shared__ real lds[NF][BLOCK];
-    __shared__ real xch[NX][BLOCK];
+    constexpr bool SYM = Shape::SYM;
+    constexpr int NPRIM = Shape::NPRIM;
+    constexpr int KSELF = Shape::KSELF;
+    real *lds = smem;                // [NF][BLK]
+    real *xch = smem + NF * BLK;     // [NX][BLK]
 
     const int tid = threadIdx.x;
     int le = tid / NP;
     const int node = tid - le * NP;
-    const long e = (long)blockIdx.x * EPB + le;
+    const long e = e0 + le;
     const bool valid = (le < EPB) && (e < t.nelem);
     if (le >= EPB) le = 0;                 // spare lanes read element 0's fields
     const long es = valid ? e : 0;
@@ -230,7 +244,7 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
         Phys::node(us, nd, ctx);
         if (i > 0) __syncthreads();       // the previous stage has finished reading LDS
 #pragma unroll
-        for (int f = 0; f < NF; ++f) lds[f][tid] = nd[f];
+        for (int f = 0; f < NF; ++f) lds[f * BLK + tid] = nd[f];
         __syncthreads();
 
         real R[M];
@@ -249,7 +263,7 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
                 const int q = line_node<N, DIM>(pd, d, qd);
                 real ndq[NF];
 #pragma unroll
-                for (int f = 0; f < NF; ++f) ndq[f] = lds[f][base + q];
+                for (int f = 0; f < NF; ++f) ndq[f] = lds[f * BLK + base + q];
                 real fs[M];
                 Phys::pair(d, nd, ndq, fs, ctx);
 #pragma unroll
@@ -257,7 +271,7 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
                 if constexpr (SYM) {
                     if (k <= NPRIM) {
 #pragma unroll
-                        for (int v = 0; v < M; ++v) xch[(d * NPRIM + (k - 1)) * M + v][tid] = fs[v];
+                        for (int v = 0; v < M; ++v) xch[((d * NPRIM + (k - 1)) * M + v) * BLK + tid] = fs[v];
                     }
                 }
             }
@@ -284,8 +298,8 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
 #pragma unroll
                 for (int q = 0; q < n1; ++q) {
                     const int qq = line_node<N, DIM>(pd, d, q);
-                    gB += Dn[d][q] * lds[5 + d][base + qq];
-                    gpsi += Dn[d][q] * lds[8][base + qq];
+                    gB += Dn[d][q] * lds[(5 + d) * BLK + base + qq];
+                    gpsi += Dn[d][q] * lds[8 * BLK + base + qq];
                 }
                 real o[M];
                 MhdP<real, FLUX>::btimes(d, nd, gB, gpsi, o);
@@ -306,7 +320,7 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
                     const int q = line_node<N, DIM>(pd, d, qd);
                     real ndq[NF], fq[M], uq[M];
 #pragma unroll
-                    for (int f = 0; f < NF; ++f) ndq[f] = lds[f][base + q];
+                    for (int f = 0; f < NF; ++f) ndq[f] = lds[f * BLK + base + q];
                     Phys::phys(d, ndq, fq, ctx);
                     Phys::cons(ndq, uq, ctx);
                     const real lam = dmax(lp, Phys::speed(d, ndq, ctx));
@@ -332,7 +346,7 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
                     const int src = base + line_node<N, DIM>(pd, d, sd);
                     const real c = Dk[d][n1 - k - 1];
 #pragma unroll
-                    for (int v = 0; v < M; ++v) R[v] += c * xch[(d * NPRIM + (k - 1)) * M + v][src];
+                    for (int v = 0; v < M; ++v) R[v] += c * xch[((d * NPRIM + (k - 1)) * M + v) * BLK + src];
                 }
         }
         // stage bookkeeping
@@ -384,14 +398,22 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
     }
 }
 
+template <typename real, int EQ, int DIM, int N, int FLUX, int S>
+__global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs a)
+{
+    constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
+    __shared__ real smem[LocalShape<real, EQ, DIM, N, FLUX>::slots * BLOCK];
+    local_tile<real, EQ, DIM, N, FLUX, S, BLOCK>(t, a, (long)blockIdx.x * (BLOCK / NP), smem);
+}
+
 // ---------------------------------------------------------------- K8 helper: modal indicator
 // Blending coefficient of one element from eps = rho*p at its nodes, one lane
 // per node: modal coefficients in the orthonormal Legendre basis, energy in
 // the highest modes, logistic map (Hennemann-Gassner form), clipping at
 // alpha_min and cap at alpha_max.  Every lane of the workgroup must call it.
-template <int DIM, int N>
+template <int DIM, int N, int BLK>
 __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le, int node, long e, bool valid,
-                                                double eps_node, double *eps, double (*en)[BLOCK], double *alpha_raw)
+                                                double eps_node, double *eps, double *en, double *alpha_raw)
 {
     constexpr int n1 = N + 1;
     constexpr int NP = DIM == 2 ? n1 * n1 : n1;
@@ -424,16 +446,16 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
         }
     }
     const double e2 = m * m;
-    en[0][tid] = e2;
-    en[1][tid] = (mk <= N - 1 && ml <= N - 1) ? e2 : 0.0;
-    en[2][tid] = (mk <= N - 2 && ml <= N - 2) ? e2 : 0.0;
+    en[tid] = e2;
+    en[BLK + tid] = (mk <= N - 1 && ml <= N - 1) ? e2 : 0.0;
+    en[2 * BLK + tid] = (mk <= N - 2 && ml <= N - 2) ? e2 : 0.0;
     __syncthreads();
     if (valid && node == 0) {
         double tot = 0.0, c1 = 0.0, c2 = 0.0;
         for (int p = 0; p < NP; ++p) {
-            tot += en[0][le * NP + p];
-            c1 += en[1][le * NP + p];
-            c2 += en[2][le * NP + p];
+            tot += en[le * NP + p];
+            c1 += en[BLK + le * NP + p];
+            c2 += en[2 * BLK + le * NP + p];
         }
         const double E1 = (tot - c1) / tot, E2 = (c1 - c2) / c1;
         const double En = E1 > E2 ? E1 : E2;
@@ -447,16 +469,17 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
 
 // Workgroup maximum of v (all lanes call) into partials[blockIdx.x]; a
 // one-workgroup kernel finishes the reduction after the grid has drained.
-__device__ __forceinline__ void block_max_lanes(double v, double *red, double *partials)
+template <int BLK>
+__device__ __forceinline__ void block_max_lanes(double v, double *red, double *slot)
 {
     const int tid = threadIdx.x;
     red[tid] = v;
     __syncthreads();
-    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+    for (int w = BLK / 2; w > 0; w >>= 1) {
         if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
         __syncthreads();
     }
-    if (tid == 0) partials[blockIdx.x] = red[0];
+    if (tid == 0) *slot = red[0];
 }
 
 // ---------------------------------------------------------------- K3: interface + final update
@@ -464,19 +487,22 @@ __device__ __forceinline__ void block_max_lanes(double v, double *red, double *p
 // u^n at the face nodes of both sides is read from the state the step
 // started from.  In the pipelined step every lane then holds u^{n+1} of its
 // node and the workgroup computes the CFL maximum and the raw indicator.
-template <typename real, int EQ, int DIM, int N, int FLUX>
-__global__ void __launch_bounds__(BLOCK) k_interface(const Tables t, const StepPtrs a)
+// One tile of BLK lanes (elements e0 .. e0 + BLK/(N+1)^DIM - 1).  In the
+// pipelined step the tile's wave-speed maximum goes to partials[slot]; dsmem
+// holds 5 * BLK doubles.
+template <typename real, int EQ, int DIM, int N, int FLUX, int BLK>
+__device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &a, long e0, long slot, double *dsmem)
 {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
     constexpr int n1 = N + 1;
     constexpr int NP = DIM == 2 ? n1 * n1 : n1;
-    constexpr int EPB = BLOCK / NP;
+    constexpr int EPB = BLK / NP;
     constexpr int M = Phys::M;
     constexpr int NF = Phys::NF;
     const int tid = threadIdx.x;
     int le = tid / NP;
     const int node = tid - le * NP;
-    const long e = (long)blockIdx.x * EPB + le;
+    const long e = e0 + le;
     const bool valid = (le < EPB) && (e < t.nelem);
     if (le >= EPB) le = 0;
     const long es = valid ? e : 0;
@@ -576,7 +602,6 @@ __global__ void __launch_bounds__(BLOCK) k_interface(const Tables t, const StepP
     if (!tail) return;
 
     // pipelined tail: CFL maximum and raw indicator of u^{n+1}
-    __shared__ double red[BLOCK];
     real nd[NF];
     Phys::node_basic(u, nd, ctx);
     double sp = 0.0;
@@ -589,14 +614,21 @@ __global__ void __launch_bounds__(BLOCK) k_interface(const Tables t, const StepP
     }
     if constexpr (EQ == EQ_EULER) {
         if (a.alpha_raw_out != nullptr) {
-            __shared__ double eps[BLOCK];
-            __shared__ double en[3][BLOCK];
             real rho, v[DIM], p, Ev;
             Phys::prim(nd, rho, v, p, Ev, ctx);
-            indicator_lanes<DIM, N>(t, tid, le, node, e, valid, (double)rho * (double)p, eps, en, a.alpha_raw_out);
+            indicator_lanes<DIM, N, BLK>(t, tid, le, node, e, valid, (double)rho * (double)p, dsmem + BLK,
+                                         dsmem + 2 * BLK, a.alpha_raw_out);
         }
     }
-    block_max_lanes(sp, red, a.partials);
+    block_max_lanes<BLK>(sp, dsmem, a.partials + slot);
+}
+
+template <typename real, int EQ, int DIM, int N, int FLUX>
+__global__ void __launch_bounds__(BLOCK) k_interface(const Tables t, const StepPtrs a)
+{
+    constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
+    __shared__ double dsmem[5 * BLOCK];
+    interface_tile<real, EQ, DIM, N, FLUX, BLOCK>(t, a, (long)blockIdx.x * (BLOCK / NP), blockIdx.x, dsmem);
 }
 
 // ---------------------------------------------------------------- K1: time step
@@ -669,7 +701,7 @@ __global__ void __launch_bounds__(BLOCK) k_indicator(const Tables t, const void 
     constexpr int NP = DIM == 2 ? n1 * n1 : n1;
     constexpr int EPB = BLOCK / NP;
     __shared__ double eps[BLOCK];
-    __shared__ double en[3][BLOCK];
+    __shared__ double en[3 * BLOCK];
     const int tid = threadIdx.x;
     int le = tid / NP;
     const int node = tid - le * NP;
@@ -687,7 +719,7 @@ __global__ void __launch_bounds__(BLOCK) k_indicator(const Tables t, const void 
 #pragma unroll
     for (int k = 0; k < DIM; ++k) ke += us[1 + k] * us[1 + k];
     const double p = (t.gamma - 1.0) * (us[DIM + 1] - 0.5 * ke / us[0]);
-    indicator_lanes<DIM, N>(t, tid, le, node, e, valid, us[0] * p, eps, en, alpha_raw);
+    indicator_lanes<DIM, N, BLOCK>(t, tid, le, node, e, valid, us[0] * p, eps, en, alpha_raw);
 }
 
 static __global__ void __launch_bounds__(BLOCK) k_smooth(const Tables t, const double *alpha_raw, double *alpha)
