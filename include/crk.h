@@ -177,6 +177,47 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
  * non-finite or has rho <= 0 or p <= 0 (-1 if none).  Needs the workspace. */
 crk_status crk_diagnostics(crk_solver *s, const void *u, double *out_dev, crk_stream stream);
 
+/* ---------------------------------------------------------------- learned indicator
+ * A multilayer perceptron 16 -> 64 -> 64 -> 1 (ReLU; output alpha_max *
+ * sigmoid(z)) gives the blending coefficient from the 16 modal energy
+ * fractions of rho*p of a degree-3 quadrilateral (the quantities of the
+ * modal indicator), on a log scale (crk_features).  Parameters: one vector theta of crk_mlp_param_count values,
+ * W1[64][16], b1[64], W2[64][64], b2[64], W3[64], b3, stored as BF16 for the
+ * network (FP32 arithmetic) and as FP32 master copy for training.  The
+ * paper gives no learned indicator; this replaces its modal one where the
+ * network is trusted. */
+crk_status crk_mlp_param_count(int nin, int hidden, int64_t *count);
+/* z[n] (may be NULL) and alpha[n] = alpha_max sigmoid(z) (may be NULL) of x[n][16]. */
+crk_status crk_mlp_forward(int nin, int hidden, const uint16_t *theta_bf16, const float *x, int64_t n,
+                           double alpha_max, float *z, double *alpha, crk_stream stream);
+/* grad[count] of the mean binary cross-entropy of sigmoid(z) against labels
+ * y[n] in [0,1], and the loss (device float, may be NULL).  Deterministic
+ * (fixed reduction order).  workspace: crk_mlp_grad_workspace_bytes. */
+crk_status crk_mlp_grad_workspace_bytes(int nin, int hidden, int64_t n, size_t *bytes);
+crk_status crk_mlp_loss_grad(int nin, int hidden, const uint16_t *theta_bf16, const float *x, const float *y, int64_t n,
+                             float *grad, float *loss, void *workspace, size_t ws_bytes, crk_stream stream);
+/* One Adam step (bias-corrected, step number t >= 1) on the FP32 master
+ * parameters, refreshing the BF16 copy when theta_bf16 != NULL. */
+crk_status crk_mlp_adam(int64_t count, float *theta, float *m, float *v, const float *grad, double lr, double b1,
+                        double b2, double eps, int t, uint16_t *theta_bf16, crk_stream stream);
+crk_status crk_mlp_to_bf16(int64_t count, const float *theta, uint16_t *theta_bf16, crk_stream stream);
+/* Features of the state u (FP32): features[e][node] = 1 + log10(max(f,
+ * 1e-16))/16 with f = m_kl^2 / sum m^2 the modal energy fractions of rho*p
+ * (in [0, 1]).  Needs the workspace. */
+crk_status crk_features(crk_solver *s, const void *u, float *features, crk_stream stream);
+/* Training labels (1/0 per element, FP32) of the unlimited update u_high
+ * of u_n: 1 if at a node of the element rho or p leaves
+ * [min (1 - tol), max (1 + tol)] of that quantity over the element and its
+ * face neighbours in u_n, or the update is non-finite or has rho <= 0 or
+ * p <= 0.  2D Euler. */
+crk_status crk_labels(crk_solver *s, const void *u_n, const void *u_high, double tol, float *labels, crk_stream stream);
+/* Use the network (device BF16 parameters, device feature range lo[16],
+ * hi[16]) for the blending coefficient of crk_indicator, crk_step,
+ * crk_prepare and crk_advance; where a feature is outside [lo, hi] or the
+ * output is not finite the modal coefficient is kept.  theta_bf16 = NULL
+ * restores the modal indicator.  2D Euler, degree 3, blending limiter. */
+crk_status crk_set_mlp(crk_solver *s, const uint16_t *theta_bf16, const float *feat_lo, const float *feat_hi);
+
 /* ---------------------------------------------------------------- batches
  * Many independent periodic 2D Euler meshes (degree 3 with classical RK4,
  * degree 4 with Butcher's RK5, one precision, Kennedy-Gruber or Ranocha

@@ -168,6 +168,8 @@ def lib():
             "orc_fr_rhs": (C.c_int, [P, _dp, C.c_int, _dp]),
             "orc_rkfr_step": (C.c_int, [P, _dp, C.c_double, _dp]),
             "orc_diagnostics": (C.c_int, [P, _dp, _dp]),
+            "orc_labels": (C.c_int, [P, _dp, _dp, C.c_double, _dp]),
+            "orc_feature_transform": (None, [C.c_long, _dp, _dp]),
             "orc_mlp_nparams": (C.c_long, [C.c_int, C.c_int]),
             "orc_mlp_forward": (C.c_int, [C.c_int, C.c_int, _dp, C.c_long, _dp, C.c_double, _dp, _dp]),
             "orc_mlp_loss_grad": (C.c_double, [C.c_int, C.c_int, _dp, C.c_long, _dp, _dp, _dp]),
@@ -337,6 +339,21 @@ def diagnostics(prob: Problem, u) -> dict:
     lib().orc_diagnostics(C.byref(prob.to_c()), _ptr(_f64(u)), _ptr(out))
     return {"totals": out[:M].copy(), "entropy": out[M], "min_rho": out[M + 1], "min_p": out[M + 2],
             "nonfinite": int(out[M + 3]), "first_bad": int(out[M + 4])}
+
+
+def labels(prob: Problem, un, uH, tol: float = 1e-3):
+    """A-posteriori troubled-element flags (1.0/0.0) of the unlimited update uH from un."""
+    out = np.zeros(prob.nelem)
+    lib().orc_labels(C.byref(prob.to_c()), _ptr(_f64(un)), _ptr(_f64(uH)), float(tol), _ptr(out))
+    return out
+
+
+def feature_transform(f):
+    """Learned-indicator input from modal energy fractions: 1 + log10(max(f, 1e-16))/16."""
+    f = _f64(f)
+    out = np.empty_like(f)
+    lib().orc_feature_transform(f.size, _ptr(f), _ptr(out))
+    return out
 
 
 # ---------------------------------------------------------------- MLP

@@ -1002,6 +1002,59 @@ int orc_diagnostics(const orc_problem *P, const double *u, double *out)
     return 0;
 }
 
+/* Input of the learned indicator: the modal energy fractions f on a log
+ * scale, 1 + log10(max(f, 1e-16))/16. */
+void orc_feature_transform(long n, const double *f, double *out)
+{
+    for (long k = 0; k < n; ++k) out[k] = 1.0 + log10(f[k] > 1e-16 ? f[k] : 1e-16) / 16.0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Training labels of the learned indicator (a-posteriori troubled flag): */
+/* element e is troubled (label 1) if the unlimited high-order update uH  */
+/* has, at some node, rho or p outside [m (1 - tol), M (1 + tol)] where m, */
+/* M are the min and max of that quantity over the nodes of e and of its   */
+/* face neighbours in un, tol = 1e-3; or if uH is non-finite or has       */
+/* rho <= 0 or p <= 0 there.  (The paper does not give a learned          */
+/* indicator; this is the target its blending coefficient is trained on.) */
+/* ------------------------------------------------------------------ */
+int orc_labels(const orc_problem *P, const double *un, const double *uH, double tol, double *labels)
+{
+    int M = orc_nvar(P), np = np_of(P);
+    long E = nelem_of(P);
+    for (long e = 0; e < E; ++e) {
+        double rmin = INFINITY, rmax = -INFINITY, pmin = INFINITY, pmax = -INFINITY;
+        long list[5];
+        int nl = 0;
+        list[nl++] = e;
+        for (int d = 0; d < P->dim; ++d)
+            for (int side = 0; side < 2; ++side) list[nl++] = neighbour(P, e, d, side);
+        for (int k = 0; k < nl; ++k) {
+            double ue[ORC_MAXNP * ORC_MAXM];
+            gather_elem(P, un, list[k], ue);
+            for (int p = 0; p < np; ++p) {
+                double r = ue[p * M], pr = orc_pressure(P, ue + p * M);
+                if (r < rmin) rmin = r;
+                if (r > rmax) rmax = r;
+                if (pr < pmin) pmin = pr;
+                if (pr > pmax) pmax = pr;
+            }
+        }
+        double uh[ORC_MAXNP * ORC_MAXM];
+        gather_elem(P, uH, e, uh);
+        int bad = 0;
+        for (int p = 0; p < np; ++p) {
+            for (int v = 0; v < M; ++v) if (!isfinite(uh[p * M + v])) bad = 1;
+            double r = uh[p * M], pr = orc_pressure(P, uh + p * M);
+            if (!(r > 0.0) || !(pr > 0.0)) bad = 1;
+            if (r < rmin * (1.0 - tol) || r > rmax * (1.0 + tol)) bad = 1;
+            if (pr < pmin * (1.0 - tol) || pr > pmax * (1.0 + tol)) bad = 1;
+        }
+        labels[e] = bad ? 1.0 : 0.0;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Learned troubled-cell indicator: MLP nin -> H -> H -> 1 with ReLU and   */
 /* output alpha_max * sigmoid(z).  Parameters packed as                    */

@@ -334,3 +334,121 @@ class Batch:
 
     def launch_graph(self):
         _check(lib().crk_batch_graph_launch(self._h, self._s()), "crk_batch_graph_launch")
+
+
+def _bind_mlp_functions(L):
+    st = C.c_int
+    sig = {
+        "crk_mlp_param_count": (st, [C.c_int, C.c_int, C.POINTER(C.c_int64)]),
+        "crk_mlp_forward": (st, [C.c_int, C.c_int, _vp, _vp, C.c_int64, C.c_double, _vp, _vp, _vp]),
+        "crk_mlp_grad_workspace_bytes": (st, [C.c_int, C.c_int, C.c_int64, C.POINTER(C.c_size_t)]),
+        "crk_mlp_loss_grad": (st, [C.c_int, C.c_int, _vp, _vp, _vp, C.c_int64, _vp, _vp, _vp, C.c_size_t, _vp]),
+        "crk_mlp_adam": (st, [C.c_int64, _vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, C.c_double,
+                              C.c_int, _vp, _vp]),
+        "crk_mlp_to_bf16": (st, [C.c_int64, _vp, _vp, _vp]),
+        "crk_features": (st, [_vp, _vp, _vp, _vp]),
+        "crk_labels": (st, [_vp, _vp, _vp, C.c_double, _vp, _vp]),
+        "crk_set_mlp": (st, [_vp, _vp, _vp, _vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+class MLP:
+    """Learned troubled-cell indicator 16 -> 64 -> 64 -> 1 on the GPU: FP32
+    master parameters, their BF16 copy used by the network, Adam moments, and
+    the feature range of the training set (outside it the modal indicator is
+    kept).  All arithmetic runs in the library's kernels."""
+
+    NIN, HID = 16, 64
+
+    def __init__(self, theta=None, lo=None, hi=None, seed=0, device="cuda"):
+        import numpy as np
+        import torch
+        L = lib()
+        _bind_mlp_functions(L)
+        cnt = C.c_int64()
+        _check(L.crk_mlp_param_count(self.NIN, self.HID, C.byref(cnt)), "crk_mlp_param_count")
+        self.count = cnt.value
+        self.device = torch.device(device)
+        if theta is None:
+            # He-style initialisation, seeded
+            rng = np.random.default_rng(seed)
+            parts = [rng.normal(0, np.sqrt(2.0 / self.NIN), self.HID * self.NIN), np.zeros(self.HID),
+                     rng.normal(0, np.sqrt(2.0 / self.HID), self.HID * self.HID), np.zeros(self.HID),
+                     rng.normal(0, np.sqrt(1.0 / self.HID), self.HID), np.zeros(1)]
+            theta = np.concatenate(parts)
+        self.theta = torch.tensor(np.asarray(theta, dtype=np.float32), device=self.device)
+        self.theta_bf16 = torch.empty(self.count, dtype=torch.int16, device=self.device)
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.t = 0
+        self.lo = torch.zeros(self.NIN, dtype=torch.float32, device=self.device) if lo is None else \
+            torch.tensor(np.asarray(lo, dtype=np.float32), device=self.device)
+        self.hi = torch.ones(self.NIN, dtype=torch.float32, device=self.device) if hi is None else \
+            torch.tensor(np.asarray(hi, dtype=np.float32), device=self.device)
+        self.sync_bf16()
+
+    def sync_bf16(self, stream=None):
+        _check(lib().crk_mlp_to_bf16(self.count, _ptr(self.theta), _ptr(self.theta_bf16), _stream(stream)),
+               "crk_mlp_to_bf16")
+
+    def forward(self, x, alpha_max=0.008, stream=None):
+        import torch
+        n = x.shape[0]
+        z = torch.empty(n, dtype=torch.float32, device=self.device)
+        a = torch.empty(n, dtype=torch.float64, device=self.device)
+        _check(lib().crk_mlp_forward(self.NIN, self.HID, _ptr(self.theta_bf16), _ptr(x), n, alpha_max, _ptr(z),
+                                     _ptr(a), _stream(stream)), "crk_mlp_forward")
+        return z, a
+
+    def loss_grad(self, x, y, ws=None, stream=None):
+        import torch
+        n = x.shape[0]
+        nb = C.c_size_t()
+        _check(lib().crk_mlp_grad_workspace_bytes(self.NIN, self.HID, n, C.byref(nb)), "workspace bytes")
+        if ws is None or ws.numel() < nb.value:
+            ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        g = torch.empty(self.count, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(lib().crk_mlp_loss_grad(self.NIN, self.HID, _ptr(self.theta_bf16), _ptr(x), _ptr(y), n, _ptr(g),
+                                       _ptr(loss), _ptr(ws), ws.numel(), _stream(stream)), "crk_mlp_loss_grad")
+        return loss, g, ws
+
+    def adam(self, grad, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        self.t += 1
+        _check(lib().crk_mlp_adam(self.count, _ptr(self.theta), _ptr(self.m), _ptr(self.v), _ptr(grad), lr, b1, b2,
+                                  eps, self.t, _ptr(self.theta_bf16), _stream(stream)), "crk_mlp_adam")
+
+    def bind(self, solver):
+        """Use this network for solver's blending coefficient."""
+        _check(lib().crk_set_mlp(solver._h, _ptr(self.theta_bf16), _ptr(self.lo), _ptr(self.hi)), "crk_set_mlp")
+        solver._mlp = self
+
+    def save(self, path):
+        import numpy as np
+        np.savez(path, theta=self.theta.cpu().numpy(), lo=self.lo.cpu().numpy(), hi=self.hi.cpu().numpy())
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            return cls(theta=z["theta"], lo=z["lo"], hi=z["hi"], device=device)
+
+
+def features(solver, u, stream=None):
+    import torch
+    _bind_mlp_functions(lib())
+    f = torch.empty((solver.nelem, solver.shape[2]), dtype=torch.float32, device=solver.device)
+    _check(lib().crk_features(solver._h, _ptr(u), _ptr(f), _stream(stream)), "crk_features")
+    return f
+
+
+def labels(solver, u_n, u_high, tol=1e-3, stream=None):
+    import torch
+    _bind_mlp_functions(lib())
+    out = torch.empty(solver.nelem, dtype=torch.float32, device=solver.device)
+    _check(lib().crk_labels(solver._h, _ptr(u_n), _ptr(u_high), tol, _ptr(out), _stream(stream)), "crk_labels")
+    return out

@@ -14,6 +14,13 @@
 
 using namespace crk;
 
+namespace crk {
+hipError_t launch_mlp_alpha(const uint16_t *theta, const float *features, const float *lo, const float *hi, long nelem,
+                            double alpha_max, double alpha_min, double *alpha_raw, hipStream_t s);
+hipError_t launch_labels(const Tables &t, int prec, const void *un, const void *uh, double tol, float *labels,
+                         hipStream_t s);
+}
+
 namespace {
 
 thread_local std::string g_err;
@@ -117,7 +124,9 @@ struct crk_solver {
     Tables t;
     size_t elem_bytes;
     size_t state_bytes, trace_bytes;
-    size_t off_partials, off_araw, off_alpha, off_traces, ws_bytes;
+    size_t off_partials, off_araw, off_alpha, off_features, off_traces, ws_bytes;
+    const uint16_t *mlp;          // learned indicator parameters (BF16, device) or nullptr
+    const float *mlp_lo, *mlp_hi; // feature range the network was trained on
     char *ws;
     bool prepared;   // crk_prepare has initialised the pipelined-step state of this workspace
 };
@@ -276,10 +285,13 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     s->off_partials = off; off = align256(off + sizeof(double) * nparts);
     s->off_araw = off; off = align256(off + sizeof(double) * nelem);
     s->off_alpha = off; off = align256(off + sizeof(double) * nelem);
+    s->off_features = off; off = align256(off + sizeof(float) * nelem * nnode);
     s->off_traces = off; off = align256(off + s->trace_bytes);
     s->ws_bytes = off;
     s->ws = nullptr;
     s->prepared = false;
+    s->mlp = nullptr;
+    s->mlp_lo = s->mlp_hi = nullptr;
     *out = s;
     return CRK_OK;
 }
@@ -339,13 +351,60 @@ crk_status crk_indicator(crk_solver *s, const void *u, double *alpha_raw, double
     if (!s || !u) return fail(CRK_ERR_ARG, "null argument");
     if (s->mesh.equation != CRK_EULER) return fail(CRK_ERR_UNSUPPORTED, "indicator is implemented for Euler only");
     double *araw = alpha_raw;
-    if (!araw) {
+    if (!araw || s->mlp) {
         crk_status st = need_ws(s);
         if (st) return st;
-        araw = (double *)(s->ws + s->off_araw);
     }
-    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::indicator(s->t, u, araw, alpha, (hipStream_t)stream); });
+    if (!araw) araw = (double *)(s->ws + s->off_araw);
+    float *feat = s->mlp ? (float *)(s->ws + s->off_features) : nullptr;
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::indicator(s->t, u, araw, nullptr, feat, hs); });
+    if (e == hipSuccess && s->mlp)
+        e = launch_mlp_alpha(s->mlp, feat, s->mlp_lo, s->mlp_hi, s->t.nelem, s->t.alpha_max, s->t.alpha_min, araw, hs);
+    if (e == hipSuccess && alpha) {
+        hipLaunchKernelGGL(k_smooth, dim3((s->t.nelem + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, hs, s->t,
+                           (const double *)araw, alpha);
+        e = hipGetLastError();
+    }
     return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_indicator");
+}
+
+crk_status crk_features(crk_solver *s, const void *u, float *features, crk_stream stream)
+{
+    crk_status st = need_ws(s);
+    if (st) return st;
+    if (!u || !features) return fail(CRK_ERR_ARG, "null argument");
+    if (s->mesh.equation != CRK_EULER) return fail(CRK_ERR_UNSUPPORTED, "features are defined for Euler only");
+    double *araw = (double *)(s->ws + s->off_araw);
+    hipError_t e = dispatch(s, [&](auto fam) {
+        return decltype(fam)::indicator(s->t, u, araw, nullptr, features, (hipStream_t)stream);
+    });
+    return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_features");
+}
+
+crk_status crk_labels(crk_solver *s, const void *u_n, const void *u_high, double tol, float *labels, crk_stream stream)
+{
+    if (!s || !u_n || !u_high || !labels) return fail(CRK_ERR_ARG, "null argument");
+    if (s->mesh.equation != CRK_EULER || s->mesh.dim != 2) return fail(CRK_ERR_UNSUPPORTED, "labels are for 2D Euler");
+    hipError_t e = launch_labels(s->t, s->prec, u_n, u_high, tol, labels, (hipStream_t)stream);
+    return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_labels");
+}
+
+crk_status crk_set_mlp(crk_solver *s, const uint16_t *theta_bf16, const float *feat_lo, const float *feat_hi)
+{
+    if (!s) return fail(CRK_ERR_ARG, "null solver");
+    if (!theta_bf16) {
+        s->mlp = nullptr;
+        s->mlp_lo = s->mlp_hi = nullptr;
+        return CRK_OK;
+    }
+    if (!feat_lo || !feat_hi) return fail(CRK_ERR_ARG, "the training feature range is required");
+    if (s->limiter != CRK_LIM_BLEND || s->mesh.equation != CRK_EULER || s->mesh.dim != 2 || s->t.N != 3)
+        return fail(CRK_ERR_UNSUPPORTED, "the learned indicator needs 2D Euler, degree 3, blending limiter");
+    s->mlp = theta_bf16;
+    s->mlp_lo = feat_lo;
+    s->mlp_hi = feat_hi;
+    return CRK_OK;
 }
 
 crk_status crk_local_stages(crk_solver *s, const void *u_in, const double *dt_dev, const double *alpha, void *u_out,
@@ -442,7 +501,11 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
         p.alpha_raw_out = lim ? araw : nullptr;
         p.partials = (double *)(s->ws + s->off_partials);
         p.dt_out = dt_dev;
+        p.features = (lim && s->mlp) ? (float *)(s->ws + s->off_features) : nullptr;
         e = dispatch(s, [&](auto fam) { return decltype(fam)::interface(s->t, s->flux, p, (hipStream_t)stream); });
+        if (e == hipSuccess && p.features)
+            e = launch_mlp_alpha(s->mlp, p.features, s->mlp_lo, s->mlp_hi, s->t.nelem, s->t.alpha_max,
+                                 s->t.alpha_min, araw, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(e, "crk_advance (interface phase)");
     }
     return CRK_OK;

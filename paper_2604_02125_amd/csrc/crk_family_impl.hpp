@@ -37,16 +37,17 @@ hipError_t Family<real, EQ, DIM>::interface(const Tables &t, int flux, const Ste
 }
 
 template <typename real, int EQ, int DIM>
-hipError_t Family<real, EQ, DIM>::indicator(const Tables &t, const void *u, double *araw, double *alpha, hipStream_t s)
+hipError_t Family<real, EQ, DIM>::indicator(const Tables &t, const void *u, double *araw, double *alpha, float *features,
+                                            hipStream_t s)
 {
     if constexpr (EQ != EQ_EULER) {
         return hipErrorInvalidValue;
     } else {
         switch (t.N) {
-        case 1: return launch_indicator<real, DIM, 1>(t, u, araw, alpha, s);
-        case 2: return launch_indicator<real, DIM, 2>(t, u, araw, alpha, s);
-        case 3: return launch_indicator<real, DIM, 3>(t, u, araw, alpha, s);
-        case 4: return launch_indicator<real, DIM, 4>(t, u, araw, alpha, s);
+        case 1: return launch_indicator<real, DIM, 1>(t, u, araw, alpha, features, s);
+        case 2: return launch_indicator<real, DIM, 2>(t, u, araw, alpha, features, s);
+        case 3: return launch_indicator<real, DIM, 3>(t, u, araw, alpha, features, s);
+        case 4: return launch_indicator<real, DIM, 4>(t, u, araw, alpha, features, s);
         default: return hipErrorInvalidValue;
         }
     }

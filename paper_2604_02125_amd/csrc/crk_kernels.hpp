@@ -48,6 +48,7 @@ struct StepPtrs {
     double *alpha_raw_out;    // interface phase: raw indicator of u_out, or nullptr
     double *partials;         // interface phase: per-workgroup wave-speed maxima
     double *dt_out;           // interface phase: dt and c_h of u_out (finished by k_dt_final), or nullptr
+    float *features;          // interface phase: learned-indicator features of u_out, or nullptr
 };
 
 // ---------------------------------------------------------------- helpers
@@ -413,7 +414,8 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
 // alpha_min and cap at alpha_max.  Every lane of the workgroup must call it.
 template <int DIM, int N, int BLK>
 __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le, int node, long e, bool valid,
-                                                double eps_node, double *eps, double *en, double *alpha_raw)
+                                                double eps_node, double *eps, double *en, double *alpha_raw,
+                                                float *features)
 {
     constexpr int n1 = N + 1;
     constexpr int NP = DIM == 2 ? n1 * n1 : n1;
@@ -464,6 +466,13 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
         if (al > 1.0 - t.alpha_min) al = 1.0;
         if (al > t.alpha_max) al = t.alpha_max;
         alpha_raw[e] = al;
+    }
+    // features of the learned indicator: the modal energy fractions
+    // f = m_kl^2 / sum m^2 on a log scale, 1 + log10(max(f, 1e-16))/16 in [0, 1]
+    if (features != nullptr && valid) {
+        double tot = 0.0;
+        for (int p = 0; p < NP; ++p) tot += en[le * NP + p];
+        features[e * NP + node] = (float)(1.0 + log10(fmax(e2 / tot, 1e-16)) / 16.0);
     }
 }
 
@@ -617,7 +626,7 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
             real rho, v[DIM], p, Ev;
             Phys::prim(nd, rho, v, p, Ev, ctx);
             indicator_lanes<DIM, N, BLK>(t, tid, le, node, e, valid, (double)rho * (double)p, dsmem + BLK,
-                                         dsmem + 2 * BLK, a.alpha_raw_out);
+                                         dsmem + 2 * BLK, a.alpha_raw_out, a.features);
         }
     }
     block_max_lanes<BLK>(sp, dsmem, a.partials + slot);
@@ -695,7 +704,7 @@ static __global__ void __launch_bounds__(BLOCK) k_dt_final(const Tables t, const
 
 // ---------------------------------------------------------------- K8: modal indicator
 template <typename real, int DIM, int N>
-__global__ void __launch_bounds__(BLOCK) k_indicator(const Tables t, const void *u_, double *alpha_raw)
+__global__ void __launch_bounds__(BLOCK) k_indicator(const Tables t, const void *u_, double *alpha_raw, float *features)
 {
     constexpr int n1 = N + 1;
     constexpr int NP = DIM == 2 ? n1 * n1 : n1;
@@ -719,7 +728,7 @@ __global__ void __launch_bounds__(BLOCK) k_indicator(const Tables t, const void 
 #pragma unroll
     for (int k = 0; k < DIM; ++k) ke += us[1 + k] * us[1 + k];
     const double p = (t.gamma - 1.0) * (us[DIM + 1] - 0.5 * ke / us[0]);
-    indicator_lanes<DIM, N, BLOCK>(t, tid, le, node, e, valid, us[0] * p, eps, en, alpha_raw);
+    indicator_lanes<DIM, N, BLOCK>(t, tid, le, node, e, valid, us[0] * p, eps, en, alpha_raw, features);
 }
 
 static __global__ void __launch_bounds__(BLOCK) k_smooth(const Tables t, const double *alpha_raw, double *alpha)
@@ -846,12 +855,12 @@ hipError_t launch_interface(const Tables &t, const StepPtrs &p, hipStream_t s)
 }
 
 template <typename real, int DIM, int N>
-hipError_t launch_indicator(const Tables &t, const void *u, double *araw, double *alpha, hipStream_t s)
+hipError_t launch_indicator(const Tables &t, const void *u, double *araw, double *alpha, float *features, hipStream_t s)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     constexpr int EPB = BLOCK / NP;
     const int grid = (t.nelem + EPB - 1) / EPB;
-    hipLaunchKernelGGL((k_indicator<real, DIM, N>), dim3(grid), dim3(BLOCK), 0, s, t, u, araw);
+    hipLaunchKernelGGL((k_indicator<real, DIM, N>), dim3(grid), dim3(BLOCK), 0, s, t, u, araw, features);
     if (alpha)
         hipLaunchKernelGGL(k_smooth, dim3((t.nelem + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, t, (const double *)araw, alpha);
     return hipGetLastError();

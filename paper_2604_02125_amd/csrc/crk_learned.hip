@@ -1,0 +1,422 @@
+// crk_learned.hip -- learned troubled-cell indicator for the blending limiter:
+// a multilayer perceptron nin -> H -> H -> 1 (ReLU, output alpha_max *
+// sigmoid) on the modal energy fractions of rho*p, with BF16 parameters and
+// FP32 arithmetic; its training kernels (loss gradient, Adam), the training
+// labels (a-posteriori troubled elements) and the inference that replaces the
+// modal blending coefficient, falling back to it where the network is not
+// trusted.  Parameter vector layout (P values):
+//   W1[H][nin], b1[H], W2[H][H], b2[H], W3[H], b3.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+
+#include "../../include/crk.h"
+#include "crk_kernels.hpp"
+
+using namespace crk;
+
+namespace crk {
+const char *set_error(crk_status st, const char *msg);
+}
+
+namespace {
+
+constexpr int NIN = 16;   // (N+1)^2 features of a degree-3 quadrilateral
+constexpr int HID = 64;
+constexpr long NPAR = (long)HID * NIN + HID + (long)HID * HID + HID + HID + 1;
+constexpr int SB = 32;    // samples per workgroup of the gradient kernel
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+struct MlpView {
+    const uint16_t *W1, *b1, *W2, *b2, *W3, *b3;
+};
+__device__ __forceinline__ MlpView mlp_view(const uint16_t *th)
+{
+    MlpView v;
+    v.W1 = th;
+    v.b1 = v.W1 + HID * NIN;
+    v.W2 = v.b1 + HID;
+    v.b2 = v.W2 + HID * HID;
+    v.W3 = v.b2 + HID;
+    v.b3 = v.W3 + HID;
+    return v;
+}
+
+// z of one sample; the weights are read at lane-uniform addresses (scalar loads)
+__device__ __forceinline__ float mlp_z(const MlpView &w, const float *x)
+{
+    float h1[HID];
+#pragma unroll
+    for (int j = 0; j < HID; ++j) {
+        float a = bf2f(w.b1[j]);
+#pragma unroll
+        for (int c = 0; c < NIN; ++c) a = fmaf(bf2f(w.W1[j * NIN + c]), x[c], a);
+        h1[j] = a > 0.f ? a : 0.f;
+    }
+    float z = bf2f(w.b3[0]);
+    for (int k = 0; k < HID; ++k) {
+        float a = bf2f(w.b2[k]);
+#pragma unroll
+        for (int j = 0; j < HID; ++j) a = fmaf(bf2f(w.W2[k * HID + j]), h1[j], a);
+        z = fmaf(bf2f(w.W3[k]), a > 0.f ? a : 0.f, z);
+    }
+    return z;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_forward(const uint16_t *theta, const float *x, long n, float alpha_max,
+                                                     float *z_out, double *alpha_out)
+{
+    const long s = (long)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const MlpView w = mlp_view(theta);
+    float xs[NIN];
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) xs[c] = x[s * NIN + c];
+    const float z = mlp_z(w, xs);
+    if (z_out) z_out[s] = z;
+    if (alpha_out) alpha_out[s] = (double)alpha_max / (1.0 + exp(-(double)z));
+}
+
+// Gradient of the mean binary cross-entropy of sigmoid(z) against y over
+// n_total samples: one workgroup per SB samples writes its partial gradient.
+__global__ void __launch_bounds__(256) k_mlp_grad(const uint16_t *theta, const float *x, const float *y, long n,
+                                                  long n_total, float *partial, float *partial_loss)
+{
+    __shared__ float xs[SB][NIN];
+    __shared__ float A1[SB][HID], A2[SB][HID], D1[SB][HID], D2[SB][HID];
+    __shared__ float dz[SB], ls[SB];
+    const int tid = threadIdx.x;
+    const long s0 = (long)blockIdx.x * SB;
+    const MlpView w = mlp_view(theta);
+    for (int i = tid; i < SB * NIN; i += 256) {
+        const int s = i / NIN, c = i - s * NIN;
+        xs[s][c] = (s0 + s < n) ? x[(s0 + s) * NIN + c] : 0.f;
+    }
+    __syncthreads();
+    for (int i = tid; i < SB * HID; i += 256) {
+        const int s = i / HID, j = i - s * HID;
+        float a = bf2f(w.b1[j]);
+#pragma unroll
+        for (int c = 0; c < NIN; ++c) a = fmaf(bf2f(w.W1[j * NIN + c]), xs[s][c], a);
+        A1[s][j] = a;
+    }
+    __syncthreads();
+    for (int i = tid; i < SB * HID; i += 256) {
+        const int s = i / HID, k = i - s * HID;
+        float a = bf2f(w.b2[k]);
+        for (int j = 0; j < HID; ++j) a = fmaf(bf2f(w.W2[k * HID + j]), fmaxf(A1[s][j], 0.f), a);
+        A2[s][k] = a;
+    }
+    __syncthreads();
+    if (tid < SB) {
+        const int s = tid;
+        float z = bf2f(w.b3[0]);
+        for (int k = 0; k < HID; ++k) z = fmaf(bf2f(w.W3[k]), fmaxf(A2[s][k], 0.f), z);
+        const bool in = s0 + s < n;
+        const float yy = in ? y[s0 + s] : 0.f;
+        const float sg = 1.f / (1.f + expf(-z));
+        dz[s] = in ? (sg - yy) / (float)n_total : 0.f;
+        // BCE with logits, stable form: log(1 + e^z) - y z
+        ls[s] = in ? ((z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z))) - yy * z) : 0.f;
+    }
+    __syncthreads();
+    for (int i = tid; i < SB * HID; i += 256) {
+        const int s = i / HID, k = i - s * HID;
+        D2[s][k] = A2[s][k] > 0.f ? dz[s] * bf2f(w.W3[k]) : 0.f;
+    }
+    __syncthreads();
+    for (int i = tid; i < SB * HID; i += 256) {
+        const int s = i / HID, j = i - s * HID;
+        float a = 0.f;
+        for (int k = 0; k < HID; ++k) a = fmaf(bf2f(w.W2[k * HID + j]), D2[s][k], a);
+        D1[s][j] = A1[s][j] > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    float *g = partial + (long)blockIdx.x * NPAR;
+    float *gW1 = g, *gb1 = gW1 + HID * NIN, *gW2 = gb1 + HID, *gb2 = gW2 + HID * HID, *gW3 = gb2 + HID, *gb3 = gW3 + HID;
+    for (int i = tid; i < HID * NIN; i += 256) {
+        const int j = i / NIN, c = i - j * NIN;
+        float a = 0.f;
+        for (int s = 0; s < SB; ++s) a = fmaf(D1[s][j], xs[s][c], a);
+        gW1[i] = a;
+    }
+    for (int i = tid; i < HID * HID; i += 256) {
+        const int k = i / HID, j = i - k * HID;
+        float a = 0.f;
+        for (int s = 0; s < SB; ++s) a = fmaf(D2[s][k], fmaxf(A1[s][j], 0.f), a);
+        gW2[i] = a;
+    }
+    if (tid < HID) {
+        float a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        for (int s = 0; s < SB; ++s) {
+            a1 += D1[s][tid];
+            a2 += D2[s][tid];
+            a3 = fmaf(dz[s], fmaxf(A2[s][tid], 0.f), a3);
+        }
+        gb1[tid] = a1;
+        gb2[tid] = a2;
+        gW3[tid] = a3;
+    }
+    if (tid == 0) {
+        float a = 0.f, l = 0.f;
+        for (int s = 0; s < SB; ++s) {
+            a += dz[s];
+            l += ls[s];
+        }
+        gb3[0] = a;
+        partial_loss[blockIdx.x] = l;
+    }
+}
+
+// sum of the partials in workgroup order (deterministic)
+__global__ void __launch_bounds__(256) k_mlp_reduce(const float *partial, const float *partial_loss, int nblocks,
+                                                    long n_total, float *grad, float *loss)
+{
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p < NPAR) {
+        float a = 0.f;
+        for (int b = 0; b < nblocks; ++b) a += partial[(long)b * NPAR + p];
+        grad[p] = a;
+    } else if (p == NPAR && loss) {
+        float l = 0.f;
+        for (int b = 0; b < nblocks; ++b) l += partial_loss[b];
+        *loss = l / (float)n_total;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_adam(long count, float *theta, float *m, float *v, const float *g, float lr,
+                                              float b1, float b2, float eps, float c1, float c2, uint16_t *theta_bf16)
+{
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    const float th = theta[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+    theta[k] = th;
+    if (theta_bf16) theta_bf16[k] = f2bf(th);
+}
+
+__global__ void __launch_bounds__(256) k_to_bf16(long count, const float *x, uint16_t *y)
+{
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;
+    if (k < count) y[k] = f2bf(x[k]);
+}
+
+// Blending coefficient from the network where it is trusted: features inside
+// the training range [lo, hi] and a finite output; elsewhere the modal
+// coefficient already in alpha_raw stays.  alpha < alpha_min is cut to 0 as
+// for the modal indicator.
+__global__ void __launch_bounds__(256) k_mlp_alpha(const uint16_t *theta, const float *features, const float *lo,
+                                                   const float *hi, long nelem, double alpha_max, double alpha_min,
+                                                   double *alpha_raw)
+{
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nelem) return;
+    float xs[NIN];
+    bool inside = true;
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) {
+        xs[c] = features[e * NIN + c];
+        inside &= (xs[c] >= lo[c]) && (xs[c] <= hi[c]);
+    }
+    const MlpView w = mlp_view(theta);
+    const float z = mlp_z(w, xs);
+    if (!inside || !isfinite(z)) return;
+    double a = alpha_max / (1.0 + exp(-(double)z));
+    if (a < alpha_min) a = 0.0;
+    alpha_raw[e] = a;
+}
+
+// Troubled-element labels: the unlimited update uh leaves the range of rho or
+// p over the element and its face neighbours in un by more than tol
+// (relative), or is inadmissible.  One lane per node.
+template <typename real, int N>
+__global__ void __launch_bounds__(BLOCK) k_labels(const Tables t, const void *un_, const void *uh_, double tol, float *labels)
+{
+    constexpr int NP = (N + 1) * (N + 1);
+    constexpr int EPB = BLOCK / NP;
+    __shared__ double red[4][BLOCK];
+    __shared__ int bad[BLOCK];
+    const int tid = threadIdx.x;
+    int le = tid / NP;
+    const int node = tid - le * NP;
+    const long e = (long)blockIdx.x * EPB + le;
+    const bool valid = (le < EPB) && (e < t.nelem);
+    if (le >= EPB) le = 0;
+    const long es = valid ? e : 0;
+    const long E = t.nelem;
+    const real *un = (const real *)un_, *uh = (const real *)uh_;
+    auto pres = [&](const real *u, long el) {
+        const double r = u[((long)0 * E + el) * NP + node], m1 = u[((long)1 * E + el) * NP + node];
+        const double m2 = u[((long)2 * E + el) * NP + node], En = u[((long)3 * E + el) * NP + node];
+        return (t.gamma - 1.0) * (En - 0.5 * (m1 * m1 + m2 * m2) / r);
+    };
+    const Nbrs nb = neighbours(t, es);
+    long list[5] = {es, nb.n[0][0], nb.n[0][1], nb.n[1][0], nb.n[1][1]};
+    double rmin = INFINITY, rmax = -INFINITY, pmin = INFINITY, pmax = -INFINITY;
+    for (int k = 0; k < 5; ++k) {
+        const double r = un[((long)0 * E + list[k]) * NP + node], p = pres(un, list[k]);
+        rmin = fmin(rmin, r);
+        rmax = fmax(rmax, r);
+        pmin = fmin(pmin, p);
+        pmax = fmax(pmax, p);
+    }
+    red[0][tid] = rmin; red[1][tid] = rmax; red[2][tid] = pmin; red[3][tid] = pmax;
+    __syncthreads();
+    const int b0 = le * NP;
+    for (int q = 0; q < NP; ++q) {
+        rmin = fmin(rmin, red[0][b0 + q]);
+        rmax = fmax(rmax, red[1][b0 + q]);
+        pmin = fmin(pmin, red[2][b0 + q]);
+        pmax = fmax(pmax, red[3][b0 + q]);
+    }
+    int flag = 0;
+    for (int v = 0; v < 4; ++v)
+        if (!isfinite((double)uh[((long)v * E + es) * NP + node])) flag = 1;
+    const double r = uh[((long)0 * E + es) * NP + node], p = pres(uh, es);
+    if (!(r > 0.0) || !(p > 0.0)) flag = 1;
+    if (r < rmin * (1.0 - tol) || r > rmax * (1.0 + tol)) flag = 1;
+    if (p < pmin * (1.0 - tol) || p > pmax * (1.0 + tol)) flag = 1;
+    bad[tid] = flag;
+    __syncthreads();
+    if (!valid || node != 0) return;
+    int any = 0;
+    for (int q = 0; q < NP; ++q) any |= bad[b0 + q];
+    labels[e] = any ? 1.f : 0.f;
+}
+
+crk_status hip_err(hipError_t e, const char *where)
+{
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    set_error(CRK_ERR_HIP, m.c_str());
+    return CRK_ERR_HIP;
+}
+
+crk_status check_shape(int nin, int hidden)
+{
+    if (nin != NIN || hidden != HID) {
+        set_error(CRK_ERR_UNSUPPORTED, "the network is compiled for 16 inputs and 64 hidden units");
+        return CRK_ERR_UNSUPPORTED;
+    }
+    return CRK_OK;
+}
+
+inline unsigned blocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+} // namespace
+
+namespace crk {
+// used by crk_api.cpp: learned blending coefficients over the modal ones
+hipError_t launch_mlp_alpha(const uint16_t *theta, const float *features, const float *lo, const float *hi, long nelem,
+                            double alpha_max, double alpha_min, double *alpha_raw, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_alpha, dim3(blocks(nelem, 256)), dim3(256), 0, s, theta, features, lo, hi, nelem, alpha_max,
+                       alpha_min, alpha_raw);
+    return hipGetLastError();
+}
+hipError_t launch_labels(const Tables &t, int prec, const void *un, const void *uh, double tol, float *labels, hipStream_t s)
+{
+    const int NP = t.nnode;
+    const unsigned g = blocks(t.nelem, BLOCK / NP);
+    if (t.dim != 2) return hipErrorInvalidValue;
+#define CRK_LAB(R, NN) hipLaunchKernelGGL((k_labels<R, NN>), dim3(g), dim3(BLOCK), 0, s, t, un, uh, tol, labels)
+    if (prec == CRK_FP64) {
+        switch (t.N) { case 1: CRK_LAB(double, 1); break; case 2: CRK_LAB(double, 2); break;
+                       case 3: CRK_LAB(double, 3); break; default: CRK_LAB(double, 4); }
+    } else {
+        switch (t.N) { case 1: CRK_LAB(float, 1); break; case 2: CRK_LAB(float, 2); break;
+                       case 3: CRK_LAB(float, 3); break; default: CRK_LAB(float, 4); }
+    }
+#undef CRK_LAB
+    return hipGetLastError();
+}
+} // namespace crk
+
+extern "C" {
+
+crk_status crk_mlp_param_count(int nin, int hidden, int64_t *count)
+{
+    if (!count) { set_error(CRK_ERR_ARG, "null argument"); return CRK_ERR_ARG; }
+    crk_status st = check_shape(nin, hidden);
+    if (st) return st;
+    *count = NPAR;
+    return CRK_OK;
+}
+
+crk_status crk_mlp_forward(int nin, int hidden, const uint16_t *theta_bf16, const float *x, int64_t n, double alpha_max,
+                           float *z, double *alpha, crk_stream stream)
+{
+    crk_status st = check_shape(nin, hidden);
+    if (st) return st;
+    if (!theta_bf16 || !x || n < 0) { set_error(CRK_ERR_ARG, "null argument"); return CRK_ERR_ARG; }
+    if (n == 0) return CRK_OK;
+    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks(n, 256)), dim3(256), 0, (hipStream_t)stream, theta_bf16, x, (long)n,
+                       (float)alpha_max, z, alpha);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CRK_OK : hip_err(e, "crk_mlp_forward");
+}
+
+crk_status crk_mlp_grad_workspace_bytes(int nin, int hidden, int64_t n, size_t *bytes)
+{
+    crk_status st = check_shape(nin, hidden);
+    if (st) return st;
+    if (!bytes || n < 0) { set_error(CRK_ERR_ARG, "bad argument"); return CRK_ERR_ARG; }
+    const long nb = (long)blocks(n, SB);
+    *bytes = ((size_t)nb * NPAR * sizeof(float) + 255) / 256 * 256 + (size_t)nb * sizeof(float);
+    return CRK_OK;
+}
+
+crk_status crk_mlp_loss_grad(int nin, int hidden, const uint16_t *theta_bf16, const float *x, const float *y, int64_t n,
+                             float *grad, float *loss, void *workspace, size_t ws_bytes, crk_stream stream)
+{
+    crk_status st = check_shape(nin, hidden);
+    if (st) return st;
+    if (!theta_bf16 || !x || !y || !grad || !workspace || n < 1) { set_error(CRK_ERR_ARG, "null argument"); return CRK_ERR_ARG; }
+    size_t need = 0;
+    crk_mlp_grad_workspace_bytes(nin, hidden, n, &need);
+    if (ws_bytes < need) { set_error(CRK_ERR_ARG, "workspace too small"); return CRK_ERR_ARG; }
+    const unsigned nb = blocks(n, SB);
+    float *part = (float *)workspace;
+    float *pl = (float *)((char *)workspace + ((size_t)nb * NPAR * sizeof(float) + 255) / 256 * 256);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, s, theta_bf16, x, y, (long)n, (long)n, part, pl);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks(NPAR + 1, 256)), dim3(256), 0, s, (const float *)part,
+                       (const float *)pl, (int)nb, (long)n, grad, loss);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CRK_OK : hip_err(e, "crk_mlp_loss_grad");
+}
+
+crk_status crk_mlp_adam(int64_t count, float *theta, float *m, float *v, const float *grad, double lr, double b1,
+                        double b2, double eps, int t, uint16_t *theta_bf16, crk_stream stream)
+{
+    if (!theta || !m || !v || !grad || count < 1 || t < 1) { set_error(CRK_ERR_ARG, "bad argument"); return CRK_ERR_ARG; }
+    const float c1 = (float)(1.0 - std::pow(b1, t)), c2 = (float)(1.0 - std::pow(b2, t));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(count, 256)), dim3(256), 0, (hipStream_t)stream, (long)count, theta, m, v,
+                       grad, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2, theta_bf16);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CRK_OK : hip_err(e, "crk_mlp_adam");
+}
+
+crk_status crk_mlp_to_bf16(int64_t count, const float *theta, uint16_t *theta_bf16, crk_stream stream)
+{
+    if (!theta || !theta_bf16 || count < 1) { set_error(CRK_ERR_ARG, "bad argument"); return CRK_ERR_ARG; }
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks(count, 256)), dim3(256), 0, (hipStream_t)stream, (long)count, theta,
+                       theta_bf16);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CRK_OK : hip_err(e, "crk_mlp_to_bf16");
+}
+
+} // extern "C"

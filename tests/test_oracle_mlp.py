@@ -45,3 +45,36 @@ def test_adam_first_step(orc):
     orc.adam_step(theta, m, v, g, 0.01, 1)
     assert np.allclose(theta, [1.0 - 0.01 * 0.3 / (0.3 + 1e-8), -2.0 + 0.01 * 4.0 / (4.0 + 1e-8), 0.5], atol=1e-15)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_labels_special_cases(orc):
+    """Troubled-element labels: a constant state and its exact free-stream
+    update are untroubled; an overshoot, an undershoot beyond the 1e-3
+    band, a negative pressure and a NaN are each flagged in their element
+    only."""
+    prob = orc.Problem(dim=2, N=3, nx=4, ny=3)
+    u = np.zeros(prob.shape)
+    u[0], u[1], u[2], u[3] = 1.0, 0.1, 0.0, 2.5
+    assert not orc.labels(prob, u, u.copy()).any()
+    uh = u.copy()
+    uh[0, 5, 3] = 1.0 + 0.5e-3                     # inside the band
+    assert not orc.labels(prob, u, uh).any()
+    uh[0, 5, 3] = 1.0 + 2e-3                       # density overshoot
+    uh[3, 9, 0] = 0.1                              # pressure undershoot in element 9
+    uh[3, 2, 7] = -1.0                             # negative pressure in element 2
+    uh[1, 11, 1] = np.nan                          # non-finite in element 11
+    lab = orc.labels(prob, u, uh)
+    assert np.flatnonzero(lab).tolist() == [2, 5, 9, 11]
+    # the bounds include the face neighbours: a value present in a neighbour is allowed
+    u2 = u.copy()
+    u2[0, 6] = 1.5                                 # element 6 is a face neighbour of 5 (4 x 3 mesh)
+    uh2 = u2.copy()
+    uh2[0, 5, 0] = 1.4
+    assert orc.labels(prob, u2, uh2)[5] == 0.0
+    uh2[0, 5, 0] = 1.6
+    assert orc.labels(prob, u2, uh2)[5] == 1.0
+
+
+def test_feature_transform(orc):
+    f = np.array([1.0, 0.1, 1e-8, 1e-16, 1e-20, 0.0])
+    assert np.allclose(orc.feature_transform(f), [1.0, 1 - 1 / 16, 0.5, 0.0, 0.0, 0.0], atol=1e-15)
