@@ -1,16 +1,19 @@
 """Throughput benchmark of the cRKFR hot path on one MI355X.
 
-Workload (default): 2D compressible Euler, Kelvin-Helmholtz initial data on
+Headline workload: 2D compressible Euler, Kelvin-Helmholtz initial data on
 [-1,1]^2 periodic, 256 x 256 elements, degree N = 3 on Gauss-Lobatto nodes
 (1,048,576 nodal DOFs), Kennedy-Gruber volume flux, Rusanov interfaces,
 classical RK4 inner stages, CFL 0.4, subcell-FV blending limiter with
-alpha_max = 0.008, FP64.  One step = CFL time step reduction + blending
-indicator + local stages + interface exchange and final update, with the
-state resident in HBM; the time-step reduction and the indicator of the
-new state run inside the interface phase (pipelined step).  Metric: DOF-updates/s (one DOF = one solution node).
+alpha_max = 0.008, FP64.  One step = local stages + interface exchange and
+final update + CFL time-step reduction + blending indicator of the new state
+(the pipelined step; crk_prepare seeds dt and the indicator of u0), with the
+state resident in HBM.  Metric: DOF-updates/s (one DOF = one solution node).
 
-Prints one JSON line.  ``--gpus`` above 1 is rejected: this build runs on a
-single GPU.
+The same JSON line carries the variants (FP32; the batch of 512 uneven
+problems replayed as a HIP graph; Kelvin-Helmholtz 512^2 with the learned
+indicator; GLM-MHD Orszag-Tang; the 1D density wave), each with its relative
+L2 error against the FP64 CPU oracle stepped from the same initial state.
+``--gpus`` above 1 is rejected: this build runs on a single GPU.
 """
 from __future__ import annotations
 
@@ -47,12 +50,8 @@ def sources_digest() -> str:
     return h.hexdigest()
 
 
-WORKLOADS = {
-    "khi256": dict(nx=256, ny=256, degree=3, flux=1, limiter=1,
-                   desc="2D Euler Kelvin-Helmholtz 256x256, N=3, Kennedy-Gruber, blending alpha_max=0.008"),
-    "khi512": dict(nx=512, ny=512, degree=3, flux=1, limiter=1,
-                   desc="2D Euler Kelvin-Helmholtz 512x512, N=3, Kennedy-Gruber, blending alpha_max=0.008"),
-}
+KHI = dict(dim=2, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, degree=3, volume_flux=1, cfl=0.4, limiter=1,
+           alpha_max=0.008, alpha_min=1e-3)
 
 
 def k2_bytes_per_dof(M: int, dim: int, N: int, elem: int) -> float:
@@ -64,15 +63,208 @@ def k2_bytes_per_dof(M: int, dim: int, N: int, elem: int) -> float:
     return elem * (2 * M + traces / npe)
 
 
+def rel_l2(a, b):
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+class Pipelined:
+    """Pipelined stepping of one crk.Solver on torch's current stream."""
+
+    def __init__(self, solver, u0):
+        import torch
+
+        from paper_2604_02125_amd import crk
+        self.s, self.crk = solver, crk
+        self.buf = [torch.tensor(u0, dtype=solver.dtype, device="cuda"), solver.new_state()]
+        self.dt = solver.new_dt()
+        self.stream = torch.cuda.current_stream()
+        self.sp = crk._stream(self.stream)
+        self.n = 0
+        crk._check(crk.lib().crk_prepare(solver._h, crk._ptr(self.buf[0]), crk._ptr(self.dt), self.sp), "prepare")
+
+    def step(self, ev=None):
+        crk, L = self.crk, self.crk.lib()
+        ui, uo = self.buf[self.n % 2], self.buf[(self.n + 1) % 2]
+        p = crk._ptr
+        if ev is not None:
+            ev[0].record(self.stream)
+        crk._check(L.crk_advance(self.s._h, p(ui), p(uo), p(self.dt), crk.PHASE_LOCAL, self.sp), "advance/local")
+        if ev is not None:
+            ev[1].record(self.stream)
+        crk._check(L.crk_advance(self.s._h, p(ui), p(uo), p(self.dt), crk.PHASE_INTERFACE, self.sp), "advance/iface")
+        self.n += 1
+
+    @property
+    def state(self):
+        return self.buf[self.n % 2]
+
+
+def timed(pipe, steps, warmup, events=False):
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)] \
+        if events else [None] * steps
+    t0 = time.perf_counter()
+    for k in range(steps):
+        pipe.step(evs[k])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    k2 = float(np.mean([a.elapsed_time(b) for a, b in evs])) if events else None
+    return el, k2
+
+
+def check_admissible(solver, u, what):
+    import numpy as np
+    d = solver.diagnostics(u).cpu().numpy()
+    M = solver.shape[0]
+    if not np.isfinite(d[:M]).all() or d[M + 3] > 0 or d[M + 4] >= 0:
+        print(f"bench: non-physical state after {what}", file=sys.stderr)
+        sys.exit(3)
+
+
+def oracle_steps(prob, u0, nsteps):
+    import oracle as orc
+    u = u0
+    for _ in range(nsteps):
+        if prob.eq == orc.MHD:
+            prob.ch = orc.compute_ch(prob, u)
+        u, _ = orc.crk_step(prob, u, orc.compute_dt(prob, u))
+    return u
+
+
+def gpu_steps(solver, u0, nsteps):
+    pipe = Pipelined(solver, u0)
+    for _ in range(nsteps):
+        pipe.step()
+    return pipe.state.double().cpu().numpy()
+
+
+def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, threads, learned=False):
+    import numpy as np
+    s = crk.Solver(nx=n, ny=n, precision=precision, **KHI)
+    if learned:
+        net = crk.MLP.load(os.path.join(ROOT, "paper_2604_02125_amd", "mlp_indicator.npz"))
+        net.bind(s)
+    xi, _, _ = crk.reference_element(3)
+    u0 = inputs.kelvin_helmholtz(n, n, xi)
+    pipe = Pipelined(s, u0)
+    el, _ = timed(pipe, steps, warmup)
+    check_admissible(s, pipe.state, f"khi{n}")
+    ndof = s.nelem * s.shape[2]
+    out = {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps}
+    if err_steps:
+        p = orc.Problem(dim=2, nx=n, ny=n, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=orc.VOL_KG,
+                        limiter=orc.LIM_BLEND_MODAL, nthreads=threads)
+        oxi, _ = orc.gll(3)
+        ref = oracle_steps(p, inputs.kelvin_helmholtz(n, n, oxi), err_steps)
+        out["l2_rel_error_vs_fp64_oracle"] = rel_l2(gpu_steps(s, u0, err_steps), ref)
+        out["error_after_steps"] = err_steps
+        if learned:
+            s2 = crk.Solver(nx=n, ny=n, precision=precision, **KHI)
+            pa = Pipelined(s2, u0)
+            for _ in range(err_steps):
+                pa.step()
+            a_modal = s2.indicator(pa.state)[1].cpu().numpy()
+            a_net = s.indicator(pa.state)[1].cpu().numpy()
+            out["alpha_positive_disagreement_vs_modal"] = float(np.mean((a_modal > 0) != (a_net > 0)))
+    return out
+
+
+def variant_batch(crk, inputs, orc, precision, reps, err_sample=4):
+    import numpy as np
+    import torch
+    specs, rng = inputs.random_fourier_problems(512, seed=20260402)
+    b = crk.Batch(specs, precision=precision, volume_flux=crk.VOL_RANOCHA)
+    states = []
+    for i, (n, N) in enumerate(specs):
+        xi, _, _ = crk.reference_element(N)
+        u = inputs.random_fourier_state(rng, n, xi)
+        if i < err_sample:
+            states.append(u)
+        b.view(0, i).copy_(torch.tensor(u, dtype=b.dtype))
+    u_init = b.u[0].clone()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(b.stream):
+        b.prepare(0)
+        b.capture_graph()
+        b.launch_graph()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        for _ in range(reps):
+            b.launch_graph()
+        e1.record(b.stream)
+    b.stream.synchronize()
+    ms = e0.elapsed_time(e1) / (2 * reps)
+    # error: two eager steps from the initial states against the oracle
+    b.u[0].copy_(u_init)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(b.stream):
+        b.prepare(0)
+        b.advance(0)
+        b.advance(1)
+    b.stream.synchronize()
+    num = den = 0.0
+    for i in range(err_sample):
+        n, N = specs[i]
+        p = orc.Problem(dim=2, nx=n, ny=n, N=N, vol_flux=orc.VOL_RANOCHA)
+        ref = oracle_steps(p, states[i], 2)
+        got = b.view(0, i).double().cpu().numpy()
+        num += float(np.sum((got - ref) ** 2))
+        den += float(np.sum(ref ** 2))
+    return {"value": b.ndof / (ms * 1e-3), "unit": "DOF-updates/s", "ms_per_step": ms, "steps": 2 * reps,
+            "problems": len(specs), "dofs": b.ndof, "tuning": {"block": b.tuning[0], "grid_per_cu": b.tuning[1]},
+            "graph": "2 pipelined steps per replay",
+            "l2_rel_error_vs_fp64_oracle": float(np.sqrt(num / den)),
+            "error_after_steps": 2, "error_sample": f"first {err_sample} problems"}
+
+
+def variant_mhd(crk, inputs, orc, precision, steps, warmup, threads):
+    n = 192
+    s = crk.Solver(dim=2, nx=n, ny=n, degree=4, equation=crk.CRK_GLM_MHD, gamma=5.0 / 3.0, precision=precision,
+                   volume_flux=crk.VOL_DERIGS, cfl=0.4)
+    xi, _, _ = crk.reference_element(4)
+    u0 = inputs.orszag_tang(n, n, xi)
+    pipe = Pipelined(s, u0)
+    el, _ = timed(pipe, steps, warmup)
+    check_admissible(s, pipe.state, "mhd")
+    p = orc.Problem(dim=2, nx=n, ny=n, N=4, eq=orc.MHD, gamma=5.0 / 3.0, vol_flux=orc.VOL_DERIGS, nthreads=threads)
+    oxi, _ = orc.gll(4)
+    ref = oracle_steps(p, inputs.orszag_tang(n, n, oxi), 1)
+    ndof = s.nelem * s.shape[2]
+    return {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
+            "l2_rel_error_vs_fp64_oracle": rel_l2(gpu_steps(s, u0, 1), ref), "error_after_steps": 1}
+
+
+def variant_wave1d(crk, inputs, orc):
+    import numpy as np
+    s = crk.Solver(dim=1, nx=64, degree=3, volume_flux=crk.VOL_RANOCHA, cfl=0.4)
+    xi, _, _ = crk.reference_element(3)
+    u0 = inputs.density_wave_1d(64, xi)
+    pipe = Pipelined(s, u0)
+    el, _ = timed(pipe, 200, 0)
+    p = orc.Problem(dim=1, nx=64, N=3, vol_flux=orc.VOL_RANOCHA)
+    oxi, _ = orc.gll(3)
+    ref = oracle_steps(p, inputs.density_wave_1d(64, oxi), 200)
+    got = pipe.state.cpu().numpy()
+    return {"value": 256 * 200 / el, "unit": "DOF-updates/s", "us_per_step": el / 200 * 1e6, "steps": 200,
+            "l2_rel_error_vs_fp64_oracle": rel_l2(got, ref), "error_after_steps": 200,
+            "max_velocity_deviation": float(np.max(np.abs(got[1] / got[0] - 0.1)))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="khi256", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--err-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
@@ -80,7 +272,6 @@ def main():
         print("bench.py runs on one GPU only (no multi-GPU path in this build); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.calibrate_copy:
@@ -94,58 +285,22 @@ def main():
         return
 
     from paper_2604_02125_amd import crk, inputs
-
-    w = WORKLOADS[args.workload]
-    prec = crk.FP64 if args.precision == "fp64" else crk.FP32
-    elem = 8 if prec == crk.FP64 else 4
     torch.cuda.set_device(0)
-    s = crk.Solver(dim=2, nx=w["nx"], ny=w["ny"], x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, degree=w["degree"],
-                   precision=prec, volume_flux=w["flux"], cfl=0.4, limiter=w["limiter"], alpha_max=0.008,
-                   alpha_min=1e-3)
-    xi, _, _ = crk.reference_element(w["degree"])
-    u0 = inputs.kelvin_helmholtz(w["nx"], w["ny"], xi)
+    threads = min(16, os.cpu_count() or 1)
+
+    # ------------------------------------------------------------ headline
+    s = crk.Solver(nx=256, ny=256, precision=crk.FP64, **KHI)
+    xi, _, _ = crk.reference_element(3)
+    u0 = inputs.kelvin_helmholtz(256, 256, xi)
     M, E, NP = s.shape
     ndof = E * NP
-    buf = [torch.tensor(u0, dtype=s.dtype, device="cuda"), s.new_state()]
-    dt = s.new_dt()
-    stream = torch.cuda.current_stream()
-    L = crk.lib()
-    h = s._h
-    ptr = crk._ptr
-    sp = crk._stream(stream)
-
-    def step(n, ev=None):
-        # pipelined step: dt and the blending indicator of the new state are
-        # computed by the interface phase (crk_prepare seeded them for u0)
-        ui, uo = buf[n % 2], buf[(n + 1) % 2]
-        if ev is not None:
-            ev[0].record(stream)
-        crk._check(L.crk_advance(h, ptr(ui), ptr(uo), ptr(dt), crk.PHASE_LOCAL, sp), "advance/local")
-        if ev is not None:
-            ev[1].record(stream)
-        crk._check(L.crk_advance(h, ptr(ui), ptr(uo), ptr(dt), crk.PHASE_INTERFACE, sp), "advance/interface")
-
-    crk._check(L.crk_prepare(h, ptr(buf[0]), ptr(dt), sp), "prepare")
-    for n in range(args.warmup):
-        step(n)
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for n in range(args.steps):
-        step(args.warmup + n, evs[n])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    k2_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    diag = s.diagnostics(buf[(args.warmup + args.steps) % 2]).cpu().numpy()
-    if not np.isfinite(diag).all() or diag[M + 4] >= 0:
-        print("bench: non-physical state after the timed steps", file=sys.stderr)
-        sys.exit(3)
-
+    pipe = Pipelined(s, u0)
+    elapsed, k2_ms = timed(pipe, args.steps, args.warmup, events=True)
+    check_admissible(s, pipe.state, "the timed steps")
     value = ndof * args.steps / elapsed
-    kb = k2_bytes_per_dof(M, 2, w["degree"], elem) * ndof
+    kb = k2_bytes_per_dof(M, 2, 3, 8) * ndof
     achieved = kb / (k2_ms * 1e-3) / 1e9
-    rec = MEASURED_TRAFFIC.get((args.workload, args.precision))
+    rec = MEASURED_TRAFFIC.get(("khi256", "fp64"))
     traffic = rec["bytes"] if rec and rec["sources_sha256"] == sources_digest() else None
     out = {
         "metric": "DOF-updates/s at 1 GPU",
@@ -158,30 +313,43 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == crk.FP64 else "f32",
+        "dtype": "f64",
         "data": "synthetic (analytic Kelvin-Helmholtz initial condition)",
-        "config": {"workload": w["desc"], "elements": E, "degree": w["degree"], "dofs": ndof,
-                   "precision": args.precision, "parallelism": "single GPU"},
+        "config": {"workload": "2D Euler Kelvin-Helmholtz 256x256, N=3, Kennedy-Gruber, blending alpha_max=0.008",
+                   "elements": E, "degree": 3, "dofs": ndof, "precision": "fp64", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_local (local stages)", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic, "kernel_ms": k2_ms,
-                     "algorithmic_bytes_per_launch": kb},
+                     "traffic": traffic, "kernel_ms": k2_ms, "algorithmic_bytes_per_launch": kb},
     }
+    import oracle as orc
     if not args.no_cpu_baseline:
-        import oracle as orc
-        nthreads = min(16, os.cpu_count() or 1)
-        p = orc.Problem(dim=2, nx=w["nx"], ny=w["ny"], x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=w["degree"],
-                        vol_flux=w["flux"], limiter=orc.LIM_BLEND_MODAL if w["limiter"] else 0, nthreads=nthreads)
-        oxi, _ = orc.gll(w["degree"])
-        uc = inputs.kelvin_helmholtz(w["nx"], w["ny"], oxi)
+        p = orc.Problem(dim=2, nx=256, ny=256, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=orc.VOL_KG,
+                        limiter=orc.LIM_BLEND_MODAL, nthreads=threads)
+        oxi, _ = orc.gll(3)
+        uc = inputs.kelvin_helmholtz(256, 256, oxi)
         c0 = time.perf_counter()
         for _ in range(args.cpu_steps):
             uc, _ = orc.crk_step(p, uc, orc.compute_dt(p, uc))
         c1 = time.perf_counter()
         out["cpu_baseline"] = {"value": ndof * args.cpu_steps / (c1 - c0), "unit": "DOF-updates/s",
-                               "cores": nthreads, "kind": "oracle",
+                               "cores": threads, "kind": "oracle",
                                "sample": f"{args.cpu_steps} full steps of the same workload (FP64 C oracle, "
-                                         f"OpenMP over elements, {nthreads} threads)"}
+                                         f"OpenMP over elements, {threads} threads)"}
+    if not args.no_variants:
+        v = {}
+        v["khi256_fp64"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps, threads)
+        v["khi256_fp32"] = variant_khi(crk, inputs, orc, 256, crk.FP32, 20, 2, args.err_steps, threads)
+        v["batch512_fp64"] = variant_batch(crk, inputs, orc, crk.FP64, 5)
+        v["batch512_fp32"] = variant_batch(crk, inputs, orc, crk.FP32, 5)
+        v["khi512_learned_fp64"] = variant_khi(crk, inputs, orc, 512, crk.FP64, 10, 2, args.err_steps, threads,
+                                               learned=True)
+        v["mhd_ot192_fp64"] = variant_mhd(crk, inputs, orc, crk.FP64, 10, 2, threads)
+        v["mhd_ot192_fp32"] = variant_mhd(crk, inputs, orc, crk.FP32, 10, 2, threads)
+        v["density_wave_1d_fp64"] = variant_wave1d(crk, inputs, orc)
+        v["_note"] = ("l2_rel_error_vs_fp64_oracle = ||u_gpu - u_oracle||_2 / ||u_oracle||_2 over all values "
+                      "after error_after_steps steps from the same initial state (the FP64 rows are a "
+                      "round-off check)")
+        out["variants"] = v
     print(json.dumps(out))
 
 
