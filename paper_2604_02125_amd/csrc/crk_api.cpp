@@ -240,6 +240,14 @@ crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables
         t.A[5][0] = -3.0 / 7; t.A[5][1] = 2.0 / 7; t.A[5][2] = 12.0 / 7; t.A[5][3] = -12.0 / 7; t.A[5][4] = 8.0 / 7;
         t.b[0] = 7.0 / 90; t.b[2] = 32.0 / 90; t.b[3] = 12.0 / 90; t.b[4] = 32.0 / 90; t.b[5] = 7.0 / 90;
     }
+    {
+        // classical RK4 gets a kernel that keeps one pending stage increment
+        const double A4[4][4] = {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {0, 0.5, 0, 0}, {0, 0, 1, 0}};
+        bool rk4 = t.stages == 4;
+        for (int i = 0; rk4 && i < 4; ++i)
+            for (int j = 0; j < 4; ++j) rk4 = rk4 && t.A[i][j] == A4[i][j];
+        t.tableau = rk4 ? 1 : 0;
+    }
     double xi[MAXN + 1], w[MAXN + 1], D[(MAXN + 1) * (MAXN + 1)];
     gll_nodes(t.N, xi, w);
     diff_matrix(t.N, xi, D);

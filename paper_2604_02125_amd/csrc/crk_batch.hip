@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(BLK) k_batch_local(const BatchProblem *probs, 
     for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
         const BatchTile tl = tiles[it];
         const BatchProblem &bp = probs[tl.prob];
-        if (bp.t.N == 3) local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK>(bp.t, bp.p[dir], tl.e0, smem);
+        if (bp.t.N == 3) local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK, 1>(bp.t, bp.p[dir], tl.e0, smem);
         else local_tile<real, EQ_EULER, 2, 4, FLUX, 6, BLK>(bp.t, bp.p[dir], tl.e0, smem);
         __syncthreads();
     }

@@ -24,6 +24,7 @@ struct Tables {
     double invdx[2];
     double gamma;
     int stages;
+    int tableau;                      // 1: classical RK4 (a_{i+1,i} only), 0: general
     double A[MAXS][MAXS];
     double b[MAXS];
     double D[MAXN + 1][MAXN + 1];     // D_pq = l_q'(xi_p) on [0,1]
@@ -130,7 +131,7 @@ struct LocalShape {
 
 // One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
 // smem holds LocalShape::slots * BLK values.
-template <typename real, int EQ, int DIM, int N, int FLUX, int S, int BLK>
+template <typename real, int EQ, int DIM, int N, int FLUX, int S, int BLK, int TAB = 0>
 __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, long e0, real *smem)
 {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
@@ -226,10 +227,12 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     }
 
     real Z[S][M];     // Z[k] = sum_{j<k} a_kj R^(j)
-    real V[M], U[M], F[DIM][M], Fnc[DIM][M], Lint[M];
+    // V accumulates (1 - alpha) sum_j b_j R^(j) + alpha L (L: interior subcell FV update)
+    real V[M], U[M], F[DIM][M], Fnc[DIM][M];
+    const real oma = real(1) - alpha;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-        V[v] = real(0); U[v] = real(0); Lint[v] = real(0);
+        V[v] = real(0); U[v] = real(0);
 #pragma unroll
         for (int k = 0; k < S; ++k) Z[k][v] = real(0);
 #pragma unroll
@@ -332,7 +335,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                     }
                 }
 #pragma unroll
-                for (int v = 0; v < M; ++v) Lint[v] += invw[d] * (fr[v] - fl[v]);
+                for (int v = 0; v < M; ++v) V[v] += alpha * invw[d] * (fr[v] - fl[v]);
             }
         }
         if constexpr (SYM) {
@@ -351,15 +354,25 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                 }
         }
         // stage bookkeeping
+        if constexpr (TAB == 1) {
+            // classical RK4: only a_{i+1,i} is non-zero
+            if (i + 1 < S) {
+                const real a1 = real(t.A[i + 1][i]);
 #pragma unroll
-        for (int k = i + 1; k < S; ++k) {
-            const real aki = real(t.A[k][i]);
+                for (int v = 0; v < M; ++v) Z[i + 1][v] = a1 * R[v];
+            }
+        } else {
 #pragma unroll
-            for (int v = 0; v < M; ++v) Z[k][v] += aki * R[v];
+            for (int k = i + 1; k < S; ++k) {
+                const real aki = real(t.A[k][i]);
+#pragma unroll
+                for (int v = 0; v < M; ++v) Z[k][v] += aki * R[v];
+            }
         }
+        const real wbi = oma * bi;
 #pragma unroll
         for (int v = 0; v < M; ++v) {
-            V[v] += bi * R[v];
+            V[v] += wbi * R[v];
             U[v] += bi * us[v];
         }
     }
@@ -368,7 +381,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     real *uout = (real *)a.u_out;
     real res[M];
 #pragma unroll
-    for (int v = 0; v < M; ++v) res[v] = un[v] - rdt * ((real(1) - alpha) * V[v] + alpha * Lint[v]);
+    for (int v = 0; v < M; ++v) res[v] = un[v] - rdt * V[v];
     if constexpr (EQ == EQ_MHD) {
         // own-side non-conservative trace term of the lifting
 #pragma unroll
@@ -399,12 +412,12 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     }
 }
 
-template <typename real, int EQ, int DIM, int N, int FLUX, int S>
+template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB = 0>
 __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs a)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     __shared__ real smem[LocalShape<real, EQ, DIM, N, FLUX>::slots * BLOCK];
-    local_tile<real, EQ, DIM, N, FLUX, S, BLOCK>(t, a, (long)blockIdx.x * (BLOCK / NP), smem);
+    local_tile<real, EQ, DIM, N, FLUX, S, BLOCK, TAB>(t, a, (long)blockIdx.x * (BLOCK / NP), smem);
 }
 
 // ---------------------------------------------------------------- K8 helper: modal indicator
@@ -833,7 +846,10 @@ hipError_t launch_local(const Tables &t, const StepPtrs &p, hipStream_t s)
     case 1: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 1>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
     case 2: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 2>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
     case 3: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 3>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
-    case 4: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
+    case 4:
+        if (t.tableau == 1) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 1>), dim3(grid), dim3(BLOCK), 0, s, t, p);
+        else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4>), dim3(grid), dim3(BLOCK), 0, s, t, p);
+        break;
     case 5: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 5>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
     case 6: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
     default: return hipErrorInvalidValue;
