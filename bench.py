@@ -55,12 +55,14 @@ KHI = dict(dim=2, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, degree=3, volume_flux=1, cfl
 
 
 def k2_bytes_per_dof(M: int, dim: int, N: int, elem: int) -> float:
-    """Algorithmic HBM bytes of the local-stage kernel per DOF: read u^n, write
-    the provisional state, write the face traces (U, F: 2M values per face
-    node, 2*dim faces of (N+1)^(dim-1) nodes per element)."""
+    """Algorithmic HBM bytes of the local-stage kernel per DOF: read u^n,
+    write the provisional state, read u^n of the face neighbours at the
+    facing nodes and write the element's share of the interface flux (M
+    values each per face node, 2*dim faces of (N+1)^(dim-1) nodes per
+    element)."""
     npe = (N + 1) ** dim
-    traces = 2 * dim * (N + 1) ** (dim - 1) * 2 * M
-    return elem * (2 * M + traces / npe)
+    face_nodes = 2 * dim * (N + 1) ** (dim - 1)
+    return elem * (2 * M + 2 * M * face_nodes / npe)
 
 
 def rel_l2(a, b):
@@ -101,20 +103,24 @@ class Pipelined:
         return self.buf[self.n % 2]
 
 
-def timed(pipe, steps, warmup, events=False):
+def timed(pipe, steps, warmup, events=False, every=4):
+    """Wall time of `steps` pipelined steps; with events, the mean duration of
+    the local-stage kernel from HIP events around it on every `every`-th step
+    of the same timed region (events on every step would add their own
+    overhead to the step time)."""
     import numpy as np
     import torch
     for _ in range(warmup):
         pipe.step()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)] \
-        if events else [None] * steps
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           if events and k % every == 0 else None for k in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
         pipe.step(evs[k])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    k2 = float(np.mean([a.elapsed_time(b) for a, b in evs])) if events else None
+    k2 = float(np.mean([e[0].elapsed_time(e[1]) for e in evs if e is not None])) if events else None
     return el, k2
 
 

@@ -95,12 +95,22 @@ crk_status crk_destroy(crk_solver *s);
 /* Sizes: nvar, nelem, nodes per element, bytes of one state array. */
 crk_status crk_state_layout(const crk_solver *s, int64_t *nvar, int64_t *nelem, int64_t *nnode, size_t *bytes);
 
-/* Face traces handed from the local-stage phase to the interface phase:
- * trace[face][c][e][k] with face = 2*d + side (side 0: xi_d = 0, side 1:
- * xi_d = 1), c < 2*nvar: U = sum_j b_j u^(j) (c < nvar), F = sum_j b_j
- * f_d(u^(j)) (nvar <= c < 2 nvar) (eq:disc.avg.flux at the face nodes);
- * k = face node (j for x faces, i for y faces; 0 in 1D).  Element type =
- * the precision. */
+/* Face data handed from the local-stage phase to the interface phase.
+ * The blended Rusanov interface flux (eq:numflux.cons) is a sum of one term
+ * per side, F* = P^- + P^+, with
+ *   P^- = (1-a)(F^-/2 + lambda U^-/2) + a(f_d(u^-)/2 + lambda u^-/2),
+ *   P^+ = (1-a)(F^+/2 - lambda U^+/2) + a(f_d(u^+)/2 - lambda u^+/2),
+ * U = sum_j b_j u^(j), F = sum_j b_j f_d(u^(j)) the time averages at the
+ * face node (eq:disc.avg.flux), u = u^n, lambda = max of the wave speeds of
+ * u^n on both sides, a = (alpha_e + alpha_nb)/2 (0 without blending).
+ * Layout trace[face][c][e][k], face = 2*d + side (side 0: xi_d = 0, side 1:
+ * xi_d = 1), k = face node (j for x faces, i for y faces; 0 in 1D):
+ * c < nvar: the element's own share P; for MHD also c = nvar: U of the
+ * normal field B_d, c = nvar + 1: U of psi; last component (c = nvar, MHD
+ * nvar + 2): the wave speed of direction d of the step's initial state at
+ * the face node, |v_d| + c (Euler) or |v_d| + c_f (MHD; lambda also takes
+ * c_h), from which the local phase forms lambda.  Element type = the
+ * precision. */
 crk_status crk_trace_bytes(const crk_solver *s, size_t *bytes);
 
 /* Scratch for crk_step and the reductions (traces, blending coefficients,
@@ -129,37 +139,45 @@ crk_status crk_indicator(crk_solver *s, const void *u, double *alpha_raw, double
  * for every element the s inner stages with flux differencing, then
  *   u_out = u_in - dt [(1-alpha_e) V + alpha_e L]   (V = sum_j b_j R^(j);
  * L = interior part of the first-order subcell FV update; alpha == NULL or
- * limiter off means alpha_e = 0), plus, for MHD, the own-side
- * non-conservative trace term, and the face traces (layout above).
- * u_in and u_out must not alias. */
+ * limiter off means alpha_e = 0), and at the face nodes the element's own
+ * part of the lifting of eq:crkfr.non.cons.final: its share P of the
+ * interface flux minus (1-alpha_e) F (for MHD also its half of
+ * 1/2 B(u^n)(g(U^-) + g(U^+)) minus the own non-conservative trace), with
+ * dg_R/dxi = delta_pN/w_N, dg_L/dxi = -delta_p0/w_0; the face data (layout
+ * above) for the neighbours.  alpha (device, nelem doubles) is read for the
+ * element and its face neighbours.  The face wave speeds of u_in are written
+ * into traces first (a separate pass; the pipelined crk_advance gets them
+ * from the previous interface phase instead).  u_in and u_out must not
+ * alias. */
 crk_status crk_local_stages(crk_solver *s, const void *u_in, const double *dt_dev, const double *alpha,
                             void *u_out, void *traces, crk_stream stream);
 
-/* Interface phase (eq:numflux.cons, eq:crkfr.non.cons.final): Rusanov flux
- * of the time averages with lambda from u^n (u_in, the state the step
- * started from) on both sides of each face node, blended with the
- * first-order flux of u^n by a = (alpha_e + alpha_nb)/2 when alpha != NULL,
- * MHD flux 1/2 B(u^n_own)(g(U^-) + g(U^+)), and the lifting with
- * dg_R/dxi = delta_pN/w_N, dg_L/dxi = -delta_p0/w_0 applied to the face
- * nodes of u_inout in place (u_inout = the local phase's output). */
+/* Interface phase (eq:numflux.cons, eq:crkfr.non.cons.final): adds to
+ * every face node of u_inout (the local phase's output, in place) the
+ * lifted share P of the neighbour across each face it lies on (for MHD
+ * also 1/2 B(u^n_own) g(U_nb), which reads u_in, the state the step started
+ * from; Euler does not read u_in).  traces = the local phase's face data. */
 crk_status crk_interface_update(crk_solver *s, const void *u_in, const void *traces, const double *dt_dev,
-                                const double *alpha, void *u_inout, crk_stream stream);
+                                void *u_inout, crk_stream stream);
 
 /* One full cRKFR step u_out = step(u_in).  flags & CRK_STEP_COMPUTE_DT:
  * compute dt_dev from u_in first (else dt_dev is an input).  With the
  * limiter on, alpha_in (device, nelem doubles, final blending coefficients)
  * is used if non-NULL, else the indicator runs on u_in.  Needs the
- * workspace; u_in and u_out must not alias. */
+ * workspace; u_in and u_out must not alias.  Uses the workspace state of
+ * the pipelined calls below: after crk_step, crk_advance needs crk_prepare
+ * again (CRK_ERR_STATE otherwise). */
 #define CRK_STEP_COMPUTE_DT 1
 crk_status crk_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, const double *alpha_in,
                     int flags, crk_stream stream);
 
 /* Pipelined time stepping.  crk_prepare computes, for a state u, dt_dev
- * (as crk_compute_dt) and, with the limiter on, the raw blending indicator
- * of u, kept in the workspace.  crk_advance then performs one step
- * u_out = step(u_in) using dt_dev and the kept indicator, both of which must
- * belong to u_in (from crk_prepare or from the previous crk_advance), and
- * computes them for u_out while the new state is still in registers: on
+ * (as crk_compute_dt), the face wave speeds of u and, with the limiter on,
+ * the raw blending indicator of u, the last two kept in the workspace.
+ * crk_advance then performs one step u_out = step(u_in) using dt_dev and the
+ * kept data, all of which must belong to u_in (from crk_prepare or from the
+ * previous crk_advance), and computes them for u_out while the new state is
+ * still in registers: on
  * return dt_dev holds the time step of u_out.  The step is the same
  * arithmetic as crk_step; only the CFL reduction and the indicator move
  * into the interface phase.  `phases` selects CRK_PHASE_LOCAL and/or

@@ -165,6 +165,7 @@ def lib():
             "orc_indicator": (C.c_int, [P, _dp, _dp, _dp, _dp]),
             "orc_crk_step": (C.c_int, [P, _dp, C.c_double, _dp, _dp, _dp]),
             "orc_local_phase": (C.c_int, [P, _dp, C.c_double, _dp, _dp, _dp, _dp]),
+            "orc_face_fluxes": (C.c_int, [P, _dp, C.c_double, _dp, _dp]),
             "orc_fr_rhs": (C.c_int, [P, _dp, C.c_int, _dp]),
             "orc_rkfr_step": (C.c_int, [P, _dp, C.c_double, _dp]),
             "orc_diagnostics": (C.c_int, [P, _dp, _dp]),
@@ -317,6 +318,18 @@ def local_phase(prob: Problem, u, dt: float):
     Ut, Ft, Fnct = np.zeros(shp), np.zeros(shp), np.zeros(shp)
     lib().orc_local_phase(C.byref(prob.to_c()), _ptr(u), float(dt), _ptr(V), _ptr(Ut), _ptr(Ft), _ptr(Fnct))
     return V, Ut, Ft, Fnct
+
+
+def face_fluxes(prob: Problem, u, dt: float, alpha=None):
+    """Interface flux F* of every face node of one cRKFR step (eq:numflux.cons,
+    blended with the first-order flux of u^n when alpha is given), as
+    [e, face, k, v]."""
+    u = _f64(u)
+    nf = prob.N + 1 if prob.dim == 2 else 1
+    out = np.zeros((prob.nelem, 2 * prob.dim, nf, prob.nvar))
+    a = None if alpha is None else _f64(alpha)
+    lib().orc_face_fluxes(C.byref(prob.to_c()), _ptr(u), float(dt), None if a is None else _ptr(a), _ptr(out))
+    return out
 
 
 def fr_rhs(prob: Problem, u, surface: int = SURF_RUSANOV):

@@ -723,6 +723,36 @@ static void rusanov(const orc_problem *P, int d, double lam, const double *fL, c
     for (int v = 0; v < M; ++v) out[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
 }
 
+/* Conservative interface flux at face node k of face (d, side) of element
+ * e (eq:numflux.cons): Rusanov flux of the time averages with lambda from
+ * the u^n traces of both sides, blended with the first-order flux of u^n by
+ * a = (alpha_e + alpha_nb)/2 when alpha != NULL.  uno, unn: u^n at this
+ * face node and at the neighbour's facing node. */
+static void interface_flux(const orc_problem *P, const traces_t *T, const double *alpha, long e, long en, int d,
+                           int side, int k, const double *uno, const double *unn, double *Fnum)
+{
+    int M = orc_nvar(P), face = 2 * d + side, nface = 2 * d + (1 - side);
+    const double *Uo = T->Ut + tr_index(P, e, face, k, 0);
+    const double *Fo = T->Ft + tr_index(P, e, face, k, 0);
+    const double *Un = T->Ut + tr_index(P, en, nface, k, 0);
+    const double *Fn = T->Ft + tr_index(P, en, nface, k, 0);
+    /* left (-) and right (+) states of this interface */
+    const double *UL = side ? Uo : Un, *UR = side ? Un : Uo;
+    const double *FL = side ? Fo : Fn, *FR = side ? Fn : Fo;
+    const double *uL = side ? uno : unn, *uR = side ? unn : uno;
+    double lL = orc_wave_speed(P, d, uL), lR = orc_wave_speed(P, d, uR);
+    double lam = lL > lR ? lL : lR;
+    rusanov(P, d, lam, FL, FR, UL, UR, Fnum);
+    if (alpha) {
+        double fL[ORC_MAXM], fR[ORC_MAXM], flo[ORC_MAXM];
+        orc_phys_flux(P, d, uL, fL);
+        orc_phys_flux(P, d, uR, fR);
+        rusanov(P, d, lam, fL, fR, uL, uR, flo);
+        double a = 0.5 * (alpha[e] + alpha[en]);
+        for (int v = 0; v < M; ++v) Fnum[v] = (1.0 - a) * Fnum[v] + a * flo[v];
+    }
+}
+
 int orc_crk_step(const orc_problem *P, const double *un, double dt, const double *alpha_in,
                  double *unew, double *alpha_out)
 {
@@ -776,24 +806,11 @@ int orc_crk_step(const orc_problem *P, const double *un, double dt, const double
                     const double *Fo = T.Ft + tr_index(P, e, face, k, 0);
                     const double *Fnco = T.Fnct + tr_index(P, e, face, k, 0);
                     const double *Un = T.Ut + tr_index(P, en, nface, k, 0);
-                    const double *Fn = T.Ft + tr_index(P, en, nface, k, 0);
                     const double *uno = ue + p * M, *unn = une + pn * M;
-                    /* left (-) and right (+) states of this interface */
                     const double *UL = side ? Uo : Un, *UR = side ? Un : Uo;
-                    const double *FL = side ? Fo : Fn, *FR = side ? Fn : Fo;
-                    const double *uL = side ? uno : unn, *uR = side ? unn : uno;
-                    double lL = orc_wave_speed(P, d, uL), lR = orc_wave_speed(P, d, uR);
-                    double lam = lL > lR ? lL : lR;
                     double Fnum[ORC_MAXM];
-                    rusanov(P, d, lam, FL, FR, UL, UR, Fnum);              /* eq:numflux.cons */
-                    if (P->limiter != ORC_LIM_NONE) {
-                        double fL[ORC_MAXM], fR[ORC_MAXM], flo[ORC_MAXM];
-                        orc_phys_flux(P, d, uL, fL);
-                        orc_phys_flux(P, d, uR, fR);
-                        rusanov(P, d, lam, fL, fR, uL, uR, flo);
-                        double a = 0.5 * (alpha[e] + alpha[en]);
-                        for (int v = 0; v < M; ++v) Fnum[v] = (1.0 - a) * Fnum[v] + a * flo[v];
-                    }
+                    interface_flux(P, &T, P->limiter != ORC_LIM_NONE ? alpha : NULL, e, en, d, side, k, uno, unn,
+                                   Fnum);
                     for (int v = 0; v < M; ++v) Fstar[face][k][v] = Fnum[v];
                     /* non-conservative interface flux of the own side:
                      * 1/2 B(u^n_own) (g(U^-) + g(U^+)) */
@@ -873,6 +890,43 @@ int orc_local_phase(const orc_problem *P, const double *un, double dt, double *V
     }
     for (long e = 0; e < E; ++e) scatter_elem(P, V, e, Ve + e * np * M);
     free(Ve);
+    return 0;
+}
+
+/* Interface fluxes of one cRKFR step: Fstar[e][face][k][v] (the layout of
+ * the traces) from the local phase's time averages and u^n; alpha = NULL
+ * for no blending. */
+int orc_face_fluxes(const orc_problem *P, const double *un, double dt, const double *alpha, double *Fstar)
+{
+    refel_t r;
+    make_refel(P, &r);
+    int M = r.M, np = r.np, nf = nface_nodes(P);
+    long E = nelem_of(P), ntr = E * 2 * P->dim * nf * M;
+    traces_t T;
+    T.Ut = malloc(sizeof(double) * ntr);
+    T.Ft = malloc(sizeof(double) * ntr);
+    T.Fnct = malloc(sizeof(double) * ntr);
+    double *V = malloc(sizeof(double) * E * np * M);
+    orc_local_phase(P, un, dt, V, T.Ut, T.Ft, T.Fnct);
+#pragma omp parallel for num_threads(nthreads_of(P)) schedule(static)
+    for (long e = 0; e < E; ++e) {
+        double ue[ORC_MAXNP * ORC_MAXM], une[ORC_MAXNP * ORC_MAXM];
+        gather_elem(P, un, e, ue);
+        for (int d = 0; d < P->dim; ++d)
+            for (int side = 0; side < 2; ++side) {
+                long en = neighbour(P, e, d, side);
+                gather_elem(P, un, en, une);
+                for (int k = 0; k < nf; ++k) {
+                    int p = face_node(P, d, side, k), pn = face_node(P, d, 1 - side, k);
+                    interface_flux(P, &T, alpha, e, en, d, side, k, ue + p * M, une + pn * M,
+                                   Fstar + tr_index(P, e, 2 * d + side, k, 0));
+                }
+            }
+    }
+    free(V);
+    free(T.Ut);
+    free(T.Ft);
+    free(T.Fnct);
     return 0;
 }
 

@@ -72,7 +72,7 @@ def lib():
             "crk_compute_dt": (st, [_vp, _vp, _vp, _vp]),
             "crk_indicator": (st, [_vp, _vp, _vp, _vp, _vp]),
             "crk_local_stages": (st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-            "crk_interface_update": (st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "crk_interface_update": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
             "crk_step": (st, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp]),
             "crk_diagnostics": (st, [_vp, _vp, _vp, _vp]),
             "crk_prepare": (st, [_vp, _vp, _vp, _vp]),
@@ -167,9 +167,13 @@ class Solver:
         return torch.zeros(2, dtype=torch.float64, device=self.device)
 
     def trace_view(self, traces):
-        """[face, c, e, k] view of a trace buffer."""
+        """[face, c, e, k] view of a face-data buffer: c < nvar the element's
+        share of the interface flux; MHD: c = nvar, nvar + 1 the time-averaged
+        normal field and psi; last c: the face wave speed of the step's
+        initial state."""
         nf = self.degree + 1 if self.dim == 2 else 1
-        return traces.view(2 * self.dim, 2 * self.shape[0], self.nelem, nf)
+        nc = self.shape[0] + (2 if self.equation == CRK_GLM_MHD else 0) + 1
+        return traces.view(2 * self.dim, nc, self.nelem, nf)
 
     def _check_state(self, u):
         if u.dtype != self.dtype or tuple(u.shape) != self.shape or not u.is_contiguous() or u.device.type != "cuda":
@@ -196,11 +200,11 @@ class Solver:
         _check(lib().crk_local_stages(self._h, _ptr(u_in), _ptr(dt), _ptr(alpha), _ptr(u_out), _ptr(traces),
                                       _stream(stream)), "crk_local_stages")
 
-    def interface_update(self, u_in, traces, dt, u, alpha=None, stream=None):
+    def interface_update(self, u_in, traces, dt, u, stream=None):
         self._check_state(u_in)
         self._check_state(u)
-        _check(lib().crk_interface_update(self._h, _ptr(u_in), _ptr(traces), _ptr(dt), _ptr(alpha), _ptr(u),
-                                          _stream(stream)), "crk_interface_update")
+        _check(lib().crk_interface_update(self._h, _ptr(u_in), _ptr(traces), _ptr(dt), _ptr(u), _stream(stream)),
+               "crk_interface_update")
 
     def step(self, u_in, u_out, dt, alpha=None, compute_dt=True, stream=None):
         self._check_state(u_in)

@@ -211,6 +211,7 @@ crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables
     t.nnode = (int)nnode;
     t.nface = m->dim == 2 ? m->degree + 1 : 1;
     t.invdx[0] = m->nx / (m->x1 - m->x0);
+    t.inv_nx = 1.0 / m->nx;
     t.invdx[1] = m->dim == 2 ? m->ny / (m->y1 - m->y0) : 0.0;
     t.gamma = m->gamma;
     t.cfl = sc->cfl;
@@ -286,7 +287,10 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     const long nnode = t.nnode, nelem = t.nelem;
     s->elem_bytes = s->prec == CRK_FP64 ? 8 : 4;
     s->state_bytes = (size_t)t.M * nelem * nnode * s->elem_bytes;
-    s->trace_bytes = (size_t)2 * t.dim * 2 * t.M * nelem * t.nface * s->elem_bytes;
+    // per face node: the element's share of the interface flux (M values),
+    // for MHD also the time-averaged normal field and psi, and the wave speed
+    const int nc = t.M + (m->equation == CRK_GLM_MHD ? 2 : 0) + 1;
+    s->trace_bytes = (size_t)2 * t.dim * nc * nelem * t.nface * s->elem_bytes;
     size_t off = 0;
     const long elem_blocks = (nelem + (BLOCK / nnode) - 1) / (BLOCK / nnode);
     const long nparts = elem_blocks > RED_BLOCKS * 16 ? elem_blocks : RED_BLOCKS * 16;
@@ -424,12 +428,14 @@ crk_status crk_local_stages(crk_solver *s, const void *u_in, const double *dt_de
     StepPtrs p{};
     p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = traces;
     p.alpha = s->limiter == CRK_LIM_BLEND ? alpha : nullptr;
-    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::local(s->t, s->flux, p, (hipStream_t)stream); });
+    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::face_speed(s->t, s->flux, p, (hipStream_t)stream); });
+    if (e == hipSuccess)
+        e = dispatch(s, [&](auto fam) { return decltype(fam)::local(s->t, s->flux, p, (hipStream_t)stream); });
     return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_local_stages");
 }
 
 crk_status crk_interface_update(crk_solver *s, const void *u_in, const void *traces, const double *dt_dev,
-                                const double *alpha, void *u_inout, crk_stream stream)
+                                void *u_inout, crk_stream stream)
 {
     if (!s || !u_in || !traces || !dt_dev || !u_inout) return fail(CRK_ERR_ARG, "null argument");
     if (u_in == u_inout) return fail(CRK_ERR_ARG, "u_in and u_inout must not alias");
@@ -437,7 +443,6 @@ crk_status crk_interface_update(crk_solver *s, const void *u_in, const void *tra
         return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
     StepPtrs p{};
     p.u_in = u_in; p.u_out = u_inout; p.dt = dt_dev; p.traces = const_cast<void *>(traces);
-    p.alpha = s->limiter == CRK_LIM_BLEND ? alpha : nullptr;
     hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::interface(s->t, s->flux, p, (hipStream_t)stream); });
     return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_interface_update");
 }
@@ -464,10 +469,13 @@ crk_status crk_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev
             alpha = a;
         }
     }
+    // the workspace's face data and indicator now describe u_in: a pipelined
+    // sequence must start again from crk_prepare
+    s->prepared = false;
     void *tr = s->ws + s->off_traces;
     st = crk_local_stages(s, u_in, dt_dev, alpha, u_out, tr, stream);
     if (st) return st;
-    return crk_interface_update(s, u_in, tr, dt_dev, alpha, u_out, stream);
+    return crk_interface_update(s, u_in, tr, dt_dev, u_out, stream);
 }
 
 crk_status crk_prepare(crk_solver *s, const void *u, double *dt_dev, crk_stream stream)
@@ -476,6 +484,10 @@ crk_status crk_prepare(crk_solver *s, const void *u, double *dt_dev, crk_stream 
     if (st) return st;
     if (s->limiter == CRK_LIM_BLEND) st = crk_indicator(s, u, (double *)(s->ws + s->off_araw), nullptr, stream);
     if (st) return st;
+    StepPtrs p{};
+    p.u_in = u; p.traces = s->ws + s->off_traces;
+    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::face_speed(s->t, s->flux, p, (hipStream_t)stream); });
+    if (e != hipSuccess) return hip_fail(e, "crk_prepare");
     s->prepared = true;
     return CRK_OK;
 }
@@ -505,7 +517,6 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
     if (phases & CRK_PHASE_INTERFACE) {
         StepPtrs p{};
         p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = tr;
-        p.alpha = lim ? alpha : nullptr;
         p.alpha_raw_out = lim ? araw : nullptr;
         p.partials = (double *)(s->ws + s->off_partials);
         p.dt_out = dt_dev;

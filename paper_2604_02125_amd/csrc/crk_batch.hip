@@ -90,7 +90,9 @@ __device__ __forceinline__ double tile_speed(const Tables &t, const void *u_, lo
     return (fabs(v1) + c) * t.invdx[0] + (fabs(v2) + c) * t.invdx[1];
 }
 
-template <typename real, int BLK>
+// wave-speed maximum of every tile of state `dir` -> partials[tile], and the
+// face wave speeds of that state into the face data
+template <typename real, int FLUX, int BLK>
 __global__ void __launch_bounds__(BLK) k_batch_speed(const BatchProblem *probs, const BatchTile *tiles, int ntiles, int dir,
                                                      double *partials)
 {
@@ -99,7 +101,10 @@ __global__ void __launch_bounds__(BLK) k_batch_speed(const BatchProblem *probs, 
         const BatchTile tl = tiles[it];
         const BatchProblem &bp = probs[tl.prob];
         const int np = (bp.t.N + 1) * (bp.t.N + 1);
-        const double v = tile_speed<real, BLK>(bp.t, dir == 0 ? bp.p[0].u_in : bp.p[1].u_in, tl.e0, np);
+        const void *u = dir == 0 ? bp.p[0].u_in : bp.p[1].u_in;
+        const double v = tile_speed<real, BLK>(bp.t, u, tl.e0, np);
+        if (bp.t.N == 3) face_speed_tile<real, EQ_EULER, 2, 3, FLUX, BLK>(bp.t, u, bp.p[0].traces, tl.e0);
+        else face_speed_tile<real, EQ_EULER, 2, 4, FLUX, BLK>(bp.t, u, bp.p[0].traces, tl.e0);
         block_max_lanes<BLK>(v, red, partials + it);
         __syncthreads();
     }
@@ -156,7 +161,7 @@ hipError_t launch_phase(const crk_batch *b, int kind, int dir, hipStream_t s)
     const int g = b->grid > 0 && b->grid < nt ? b->grid : nt;
     if (kind == 0) hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir);
     else if (kind == 1) hipLaunchKernelGGL((k_batch_interface<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir);
-    else hipLaunchKernelGGL((k_batch_speed<real, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir, parts);
+    else hipLaunchKernelGGL((k_batch_speed<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir, parts);
     if (kind != 0) hipLaunchKernelGGL(k_batch_dt, dim3(b->nprob), dim3(256), 0, s, pr, (const double *)parts, b->dt);
     return hipGetLastError();
 }
@@ -244,7 +249,8 @@ crk_status crk_batch_create(const crk_mesh_desc *meshes, int nprob, const crk_sc
         b->state_off[i] = off;
         off += (long)t.M * t.nelem * t.nnode;
         b->trace_off[i] = toff;
-        toff = align256(toff + (size_t)2 * 2 * 2 * t.M * t.nelem * t.nface * elem);
+        // four faces; per face node M flux-share values and the wave speed
+        toff = align256(toff + (size_t)2 * 2 * (t.M + 1) * t.nelem * t.nface * elem);
         const int epb = block / t.nnode;
         b->probs[i].tile0 = (int)b->tiles.size();
         for (int e0 = 0; e0 < t.nelem; e0 += epb) b->tiles.push_back(BatchTile{i, e0});

@@ -37,6 +37,12 @@ hipError_t Family<real, EQ, DIM>::interface(const Tables &t, int flux, const Ste
 }
 
 template <typename real, int EQ, int DIM>
+hipError_t Family<real, EQ, DIM>::face_speed(const Tables &t, int flux, const StepPtrs &p, hipStream_t s)
+{
+    CRK_DEGREE_SWITCH(launch_face_speed)
+}
+
+template <typename real, int EQ, int DIM>
 hipError_t Family<real, EQ, DIM>::indicator(const Tables &t, const void *u, double *araw, double *alpha, float *features,
                                             hipStream_t s)
 {

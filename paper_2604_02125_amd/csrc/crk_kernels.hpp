@@ -22,6 +22,7 @@ constexpr int RED_BLOCKS = 1024;  // max workgroups of the reduction kernels
 struct Tables {
     int dim, nx, ny, N, M, nelem, nnode, nface;  // nface = nodes per face
     double invdx[2];
+    double inv_nx;                    // 1/nx, for the element coordinates
     double gamma;
     int stages;
     int tableau;                      // 1: classical RK4 (a_{i+1,i} only), 0: general
@@ -53,34 +54,32 @@ struct StepPtrs {
 };
 
 // ---------------------------------------------------------------- helpers
-__device__ __forceinline__ long neighbour(const Tables &t, long e, int d, int side)
-{
-    if (t.dim == 1) return side ? (e + 1 == t.nx ? 0 : e + 1) : (e == 0 ? t.nx - 1 : e - 1);
-    long ex = e % t.nx, ey = e / t.nx;
-    if (d == 0) ex = side ? (ex + 1 == t.nx ? 0 : ex + 1) : (ex == 0 ? t.nx - 1 : ex - 1);
-    else ey = side ? (ey + 1 == t.ny ? 0 : ey + 1) : (ey == 0 ? t.ny - 1 : ey - 1);
-    return ey * t.nx + ex;
-}
-
-// element coordinates and the four (two in 1D) face neighbours with one division
+// element coordinates and the four (two in 1D) face neighbours; e < 2^31.
+// The row index comes from a double-precision product with 1/nx (off by at
+// most one next to exact multiples, then corrected): far cheaper per lane
+// than a 64-bit integer division.
 struct Nbrs {
     long n[2][2];   // [d][side]
 };
 __device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
 {
     Nbrs r;
+    const int nx = t.nx, ei = (int)e;
     if (t.dim == 1) {
-        r.n[0][0] = e == 0 ? t.nx - 1 : e - 1;
-        r.n[0][1] = e + 1 == t.nx ? 0 : e + 1;
+        r.n[0][0] = ei == 0 ? nx - 1 : ei - 1;
+        r.n[0][1] = ei + 1 == nx ? 0 : ei + 1;
         r.n[1][0] = r.n[1][1] = e;
         return r;
     }
-    const long ey = e / t.nx, ex = e - ey * t.nx;
-    const long row = ey * t.nx;
-    r.n[0][0] = row + (ex == 0 ? t.nx - 1 : ex - 1);
-    r.n[0][1] = row + (ex + 1 == t.nx ? 0 : ex + 1);
-    r.n[1][0] = (ey == 0 ? (long)(t.ny - 1) * t.nx : row - t.nx) + ex;
-    r.n[1][1] = (ey + 1 == t.ny ? 0 : row + t.nx) + ex;
+    int ey = (int)floor((double)ei * t.inv_nx);
+    int ex = ei - ey * nx;
+    if (ex < 0) { --ey; ex += nx; }
+    else if (ex >= nx) { ++ey; ex -= nx; }
+    const int row = ey * nx;
+    r.n[0][0] = row + (ex == 0 ? nx - 1 : ex - 1);
+    r.n[0][1] = row + (ex + 1 == nx ? 0 : ex + 1);
+    r.n[1][0] = (ey == 0 ? (t.ny - 1) * nx : row - nx) + ex;
+    r.n[1][1] = (ey + 1 == t.ny ? 0 : row + nx) + ex;
     return r;
 }
 
@@ -97,6 +96,69 @@ __device__ __forceinline__ Ctx<real> make_ctx(const Tables &t, const double *dt)
     c.inv_gm1 = real(1.0 / (t.gamma - 1.0));
     c.ch = dt ? real(dt[1]) : real(0);
     return c;
+}
+
+// Face data between the two phases, [face][c][e][k] (face = 2d + side, k =
+// face node): c < M the element's share of the interface flux; MHD: c = M,
+// M + 1 the time-averaged normal field and psi; last component the wave
+// speed of direction d of the state at the face node, |v_d| + c (Euler) or
+// |v_d| + c_f (MHD), from which the local phase forms the Rusanov lambda.
+template <int EQ, int M>
+struct FaceData {
+    static constexpr int NC = EQ == EQ_MHD ? M + 2 : M;   // flux-share (+ MHD) components
+    static constexpr int SPEED = NC;                       // component of the wave speed
+    static constexpr int NCT = NC + 1;                     // components per face node
+};
+
+template <typename real, int EQ, int DIM, int FLUX>
+__device__ __forceinline__ real face_speed(int d, const real *nd, const Ctx<real> &ctx)
+{
+    if constexpr (EQ == EQ_MHD) return MhdP<real, FLUX>::fast(d, nd, ctx);
+    else return EulerP<real, DIM, FLUX>::speed(d, nd, ctx);
+}
+
+// One tile of BLK lanes (a lane per node): the wave speeds of the face nodes of u.
+template <typename real, int EQ, int DIM, int N, int FLUX, int BLK>
+__device__ __forceinline__ void face_speed_tile(const Tables &t, const void *u_, void *traces, long e0)
+{
+    using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
+    constexpr int n1 = N + 1;
+    constexpr int NP = DIM == 2 ? n1 * n1 : n1;
+    constexpr int M = Phys::M;
+    constexpr int nf = DIM == 2 ? n1 : 1;
+    using FD = FaceData<EQ, M>;
+    const int tid = threadIdx.x;
+    const int le = tid / NP;
+    const int node = tid - le * NP;
+    const long e = e0 + le;
+    if (le >= BLK / NP || e >= t.nelem) return;
+    const int pd[2] = {node % n1, DIM == 2 ? node / n1 : 0};
+    bool face_lane = false;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) face_lane |= (pd[d] == 0 || pd[d] == N);
+    if (!face_lane) return;
+    const long E = t.nelem;
+    const real *u = (const real *)u_;
+    real us[M], nd[Phys::NF];
+#pragma unroll
+    for (int v = 0; v < M; ++v) us[v] = u[((long)v * E + e) * NP + node];
+    const Ctx<real> ctx = make_ctx<real>(t, nullptr);
+    Phys::node_basic(us, nd, ctx);
+    real *tr = (real *)traces;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        if (!(pd[d] == 0 || pd[d] == N)) continue;
+        const int face = 2 * d + (pd[d] == N ? 1 : 0);
+        const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
+        tr[((long)(face * FD::NCT + FD::SPEED) * E + e) * nf + kk] = face_speed<real, EQ, DIM, FLUX>(d, nd, ctx);
+    }
+}
+
+template <typename real, int EQ, int DIM, int N, int FLUX>
+__global__ void __launch_bounds__(BLOCK) k_face_speed(const Tables t, const void *u, void *traces)
+{
+    constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
+    face_speed_tile<real, EQ, DIM, N, FLUX, BLOCK>(t, u, traces, (long)blockIdx.x * (BLOCK / NP));
 }
 
 // ---------------------------------------------------------------- K2: local stages
@@ -117,6 +179,23 @@ __device__ __forceinline__ int line_node(const int *pd, int d, int qd)
     return (DIM == 1) ? qd : (d == 0 ? pd[1] * n1 + qd : qd * n1 + pd[0]);
 }
 
+// Synchronisation of the lanes of one element.  When a wavefront holds
+// whole elements (64 divisible by (N+1)^d: N = 1, 3), every LDS exchange of
+// the local stages stays inside one wavefront, so ordering the wavefront's
+// own LDS accesses suffices and the waves of a workgroup never wait for each
+// other; otherwise the workgroup barrier.
+template <int NP>
+__device__ __forceinline__ void element_sync()
+{
+    if constexpr (64 % NP == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // LDS slots (of BLK values each) used by the local-stage tile
 template <typename real, int EQ, int DIM, int N, int FLUX>
 struct LocalShape {
@@ -126,7 +205,10 @@ struct LocalShape {
     static constexpr int NPRIM = SYM ? (n1 - 1) / 2 : 0;           // rotations whose mirror comes from LDS
     static constexpr int KSELF = (SYM && n1 % 2 == 0) ? n1 / 2 : 0;  // self-mirrored rotation, evaluated directly
     static constexpr int NX = SYM ? DIM * NPRIM * Phys::M : 0;
-    static constexpr int slots = Phys::NF + NX;
+    // two more slots carry the blending coefficients of each element and of
+    // its face neighbours ((2 DIM + 1) values per element, N + 1 >= 2), DIM
+    // slots the Rusanov speed of the faces through each node
+    static constexpr int slots = Phys::NF + NX + 2 + DIM;
 };
 
 // One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
@@ -146,6 +228,9 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     constexpr int KSELF = Shape::KSELF;
     real *lds = smem;                // [NF][BLK]
     real *xch = smem + NF * BLK;     // [NX][BLK]
+    real *alds = xch + Shape::NX * BLK;   // [EPB][2 DIM + 1]
+    real *llds = alds + 2 * BLK;          // [DIM][BLK]
+    constexpr int NA = 2 * DIM + 1;
 
     const int tid = threadIdx.x;
     int le = tid / NP;
@@ -161,24 +246,19 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     const Ctx<real> ctx = make_ctx<real>(t, a.dt);
     const real rdt = real(a.dt[0]);
 
-    // per-lane coefficients 2 D_{p,q}/dx_d of rotation k = 1..N, of the diagonal, and 1/(w_p dx_d)
+    // per-lane coefficients 2 D_{p,q}/dx_d of rotation k = 1..N, of the diagonal,
+    // and 1/(w_p dx_d), read from the tables with the lane's node index
     real Dk[DIM][N], Ddiag[DIM], invw[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
+        const int r = pd[d];
 #pragma unroll
         for (int k = 1; k <= N; ++k) {
-            real c = real(0);
-#pragma unroll
-            for (int r = 0; r < n1; ++r)
-                if (pd[d] == r) c = real(2.0 * t.D[r][(r + k) % n1] * t.invdx[d]);
-            Dk[d][k - 1] = c;
+            const int q = r + k < n1 ? r + k : r + k - n1;
+            Dk[d][k - 1] = real(2.0 * t.D[r][q] * t.invdx[d]);
         }
-        real dg = real(0), iw = real(0);
-#pragma unroll
-        for (int r = 0; r < n1; ++r)
-            if (pd[d] == r) { dg = real(2.0 * t.D[r][r] * t.invdx[d]); iw = real(t.invw_dx[d][r]); }
-        Ddiag[d] = dg;
-        invw[d] = iw;
+        Ddiag[d] = real(2.0 * t.D[r][r] * t.invdx[d]);
+        invw[d] = real(t.invw_dx[d][r]);
     }
     // MHD: plain D_pq / dx_d for the non-conservative term, all q
     real Dn[DIM][n1];
@@ -200,24 +280,6 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 #pragma unroll
     for (int v = 0; v < M; ++v) un[v] = uin[((long)v * E + es) * NP + node];
 
-    bool blend;
-    real alpha;
-    if (a.alpha_raw != nullptr) {
-        // alpha_e = max(alpha_raw_e, max over face neighbours of alpha_raw / 2)
-        blend = true;
-        double am = a.alpha_raw[es];
-        const Nbrs nb = neighbours(t, es);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d)
-#pragma unroll
-            for (int sd = 0; sd < 2; ++sd) am = fmax(am, 0.5 * a.alpha_raw[nb.n[d][sd]]);
-        alpha = valid ? real(am) : real(0);
-        if (valid && node == 0) a.alpha_s[e] = am;
-    } else {
-        blend = a.alpha != nullptr;
-        alpha = (blend && valid) ? real(a.alpha[es]) : real(0);
-    }
-
     bool onface[DIM];
     int side[DIM];
 #pragma unroll
@@ -225,11 +287,73 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         onface[d] = (pd[d] == 0) || (pd[d] == N);
         side[d] = (pd[d] == N) ? 1 : 0;
     }
+    const Nbrs nb = neighbours(t, es);
+
+    // Rusanov speed of each face through this node: lambda = max of the
+    // wave speeds of u^n on both sides (eq:numflux.cons; MHD: and c_h), from
+    // the face data, formed here so that the element can add its own share
+    // of the interface flux itself; kept in LDS until the end of the stages
+    constexpr int nfn = DIM == 2 ? n1 : 1;
+    using FD = FaceData<EQ, M>;
+    {
+        const real *ts = (const real *)a.traces;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            if (!onface[d]) continue;
+            const int face = 2 * d + side[d], nface = 2 * d + 1 - side[d];
+            const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
+            const long en = side[d] ? nb.n[d][1] : nb.n[d][0];
+            const real so = ts[((long)(face * FD::NCT + FD::SPEED) * E + es) * nfn + kk];
+            const real sn = ts[((long)(nface * FD::NCT + FD::SPEED) * E + en) * nfn + kk];
+            real lam = dmax(so, sn);
+            if constexpr (EQ == EQ_MHD) lam = dmax(lam, ctx.ch);
+            llds[d * BLK + tid] = lam;
+        }
+    }
+
+    // blending coefficients of the element (slot 0) and of its face
+    // neighbours (slot 1 + 2d + side), formed by the first lanes of the
+    // element: given (alpha), or in the pipelined step alpha_e =
+    // max(alpha_raw_e, max over face neighbours of alpha_raw / 2); read after
+    // the first stage's barrier
+    const bool smooth = a.alpha_raw != nullptr;
+    const bool blend = smooth || a.alpha != nullptr;
+    real alpha = real(0);
+    if (blend && valid) {
+#pragma unroll
+        for (int r = 0; r < (NA + NP - 1) / NP; ++r) {
+            const int j = node + r * NP;
+            if (j >= NA) break;
+            long tg = es;           // (selects, not a dynamically indexed array: no scratch)
+#pragma unroll
+            for (int c = 0; c < 2 * DIM; ++c)
+                if (j == 1 + c) tg = nb.n[c >> 1][c & 1];
+            double am;
+            if (!smooth) {
+                am = a.alpha[tg];
+            } else if (j == 0) {
+                am = a.alpha_raw[tg];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d)
+#pragma unroll
+                    for (int sd = 0; sd < 2; ++sd) am = fmax(am, 0.5 * a.alpha_raw[nb.n[d][sd]]);
+                a.alpha_s[e] = am;
+            } else {
+                const Nbrs nt = neighbours(t, tg);
+                am = a.alpha_raw[tg];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d)
+#pragma unroll
+                    for (int sd = 0; sd < 2; ++sd) am = fmax(am, 0.5 * a.alpha_raw[nt.n[d][sd]]);
+            }
+            alds[le * NA + j] = real(am);
+        }
+    }
 
     real Z[S][M];     // Z[k] = sum_{j<k} a_kj R^(j)
     // V accumulates (1 - alpha) sum_j b_j R^(j) + alpha L (L: interior subcell FV update)
     real V[M], U[M], F[DIM][M], Fnc[DIM][M];
-    const real oma = real(1) - alpha;
+    real oma = real(1) - alpha;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
         V[v] = real(0); U[v] = real(0);
@@ -246,10 +370,14 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         for (int v = 0; v < M; ++v) us[v] = (i == 0) ? un[v] : un[v] - rdt * Z[i][v];
         real nd[NF];
         Phys::node(us, nd, ctx);
-        if (i > 0) __syncthreads();       // the previous stage has finished reading LDS
+        if (i > 0) element_sync<NP>();    // the previous stage has finished reading LDS
 #pragma unroll
         for (int f = 0; f < NF; ++f) lds[f * BLK + tid] = nd[f];
-        __syncthreads();
+        element_sync<NP>();
+        if (i == 0 && blend && valid) {
+            alpha = alds[le * NA];
+            oma = real(1) - alpha;
+        }
 
         real R[M];
 #pragma unroll
@@ -339,7 +467,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
             }
         }
         if constexpr (SYM) {
-            __syncthreads();
+            element_sync<NP>();
 #pragma unroll
             for (int d = 0; d < DIM; ++d)
 #pragma unroll
@@ -378,38 +506,68 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     }
 
     if (!valid) return;
-    real *uout = (real *)a.u_out;
     real res[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) res[v] = un[v] - rdt * V[v];
-    if constexpr (EQ == EQ_MHD) {
-        // own-side non-conservative trace term of the lifting
-#pragma unroll
-        for (int d = 0; d < DIM; ++d)
-            if (onface[d]) {
-                const real sg = side[d] ? rdt * invw[d] : -rdt * invw[d];
-#pragma unroll
-                for (int v = 0; v < M; ++v) res[v] += sg * Fnc[d][v];
-            }
-    }
-#pragma unroll
-    for (int v = 0; v < M; ++v) uout[((long)v * E + e) * NP + node] = res[v];
 
-    // traces [face][c][e][k], c < 2M: U then F
+    // Interface flux, split by side.  With lambda and the face blending
+    // factor a known to both elements, the blended Rusanov flux of
+    // eq:numflux.cons is F* = P^- + P^+ with
+    //   P^- = (1-a)(F^-/2 + lambda U^-/2) + a(f(u^-)/2 + lambda u^-/2)
+    //   P^+ = (1-a)(F^+/2 - lambda U^+/2) + a(f(u^+)/2 - lambda u^+/2)
+    // (U, F: time averages at the face node, u: u^n).  The element applies
+    // its own share and its own trace term -(1-alpha_e) F of the lifting
+    // here and publishes P for the neighbour; for MHD it also applies the
+    // own half of 1/2 B(u^n)(g(U^-) + g(U^+)) and publishes g(U) (the normal
+    // field and psi).  traces[face][c][e][k], c < M: P; MHD: c = M, M + 1.
     real *tr = (real *)a.traces;
-    constexpr int nf = DIM == 2 ? n1 : 1;
+    real ndo[NF], fo[M];
+    bool have_fo = false;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         if (!onface[d]) continue;
+        const real lam = llds[d * BLK + tid];
+        const real hl = side[d] ? real(0.5) * lam : real(-0.5) * lam;
+        const real af = blend ? real(0.5) * (alds[le * NA] + alds[le * NA + 1 + 2 * d + side[d]]) : real(0);
+        const real oaf = real(1) - af;
+        real P[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) P[v] = oaf * (real(0.5) * F[d][v] + hl * U[v]);
+        if (af > real(0)) {
+            if (!have_fo) {
+                real uc[M];
+#pragma unroll
+                for (int v = 0; v < M; ++v) { uc[v] = un[v]; asm volatile("" : "+v"(uc[v])); }
+                Phys::node_basic(uc, ndo, ctx);
+                have_fo = true;
+            }
+            Phys::phys(d, ndo, fo, ctx);
+#pragma unroll
+            for (int v = 0; v < M; ++v) P[v] += af * (real(0.5) * fo[v] + hl * un[v]);
+        }
+        const real coef = side[d] ? -rdt * invw[d] : rdt * invw[d];
+#pragma unroll
+        for (int v = 0; v < M; ++v) res[v] += coef * (P[v] - oma * F[d][v]);
+        if constexpr (EQ == EQ_MHD) {
+            if (!have_fo) { Phys::node_basic(un, ndo, ctx); have_fo = true; }
+            real o[M];
+            MhdP<real, FLUX>::btimes(d, ndo, real(0.5) * U[5 + d], real(0.5) * U[8], o);
+#pragma unroll
+            for (int v = 0; v < M; ++v) res[v] += coef * (o[v] - Fnc[d][v]);
+        }
         const int face = 2 * d + side[d];
         const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
-        real *tb = tr + ((long)face * 2 * M * E + e) * nf + kk;
+        real *tb = tr + ((long)face * FD::NCT * E + e) * nfn + kk;
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-            tb[((long)v * E) * nf] = U[v];
-            tb[((long)(M + v) * E) * nf] = F[d][v];
+        for (int v = 0; v < M; ++v) tb[((long)v * E) * nfn] = P[v];
+        if constexpr (EQ == EQ_MHD) {
+            tb[((long)M * E) * nfn] = U[5 + d];
+            tb[((long)(M + 1) * E) * nfn] = U[8];
         }
     }
+    real *uout = (real *)a.u_out;
+#pragma unroll
+    for (int v = 0; v < M; ++v) uout[((long)v * E + e) * NP + node] = res[v];
 }
 
 template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB = 0>
@@ -533,12 +691,10 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
 
     const long E = t.nelem;
     constexpr int nf = DIM == 2 ? n1 : 1;
+    using FD = FaceData<EQ, M>;
     const Ctx<real> ctx = make_ctx<real>(t, a.dt);
     const real rdt = real(a.dt[0]);
-    const bool blend = a.alpha != nullptr;
-    const real alpha_e = blend ? real(a.alpha[es]) : real(0);
     const real *tr = (const real *)a.traces;
-    const real *uin = (const real *)a.u_in;
     real *uo = (real *)a.u_out;
 
     bool face_lane = false;
@@ -555,66 +711,37 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
         for (int v = 0; v < M; ++v) u[v] = real(v == 0 ? 1 : 0);
     }
     if (face_lane) {
-        real uno[M];
-#pragma unroll
-        for (int v = 0; v < M; ++v) uno[v] = uin[((long)v * E + e) * NP + node];
-        real ndo[NF];
-        Phys::node_basic(uno, ndo, ctx);
+        // the neighbour's share of the interface flux (the own share and the
+        // own trace term were applied by the local phase), lifted with
+        // dg_R/dxi = delta_pN/w_N, dg_L/dxi = -delta_p0/w_0
         const Nbrs nb = neighbours(t, e);
+        real ndo[NF];
+        if constexpr (EQ == EQ_MHD) {
+            const real *uin = (const real *)a.u_in;
+            real uno[M];
+#pragma unroll
+            for (int v = 0; v < M; ++v) uno[v] = uin[((long)v * E + e) * NP + node];
+            Phys::node_basic(uno, ndo, ctx);
+        }
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             if (!(pd[d] == 0 || pd[d] == N)) continue;
             const int side = pd[d] == N ? 1 : 0;
-            const long en = nb.n[d][side];
-            const int face = 2 * d + side, nface = 2 * d + 1 - side;
+            const long en = side ? nb.n[d][1] : nb.n[d][0];
+            const int nface = 2 * d + 1 - side;
             const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
-            int qd[2] = {pd[0], pd[1]};
-            qd[d] = N - pd[d];                      // the neighbour's node facing this one
-            const int nnode = DIM == 1 ? qd[0] : qd[1] * n1 + qd[0];
-            const real *to = tr + ((long)face * 2 * M * E + e) * nf + kk;
-            const real *tn = tr + ((long)nface * 2 * M * E + en) * nf + kk;
-            real Uo[M], Fo[M], Un[M], Fn[M], unn[M];
-#pragma unroll
-            for (int v = 0; v < M; ++v) {
-                Uo[v] = to[((long)v * E) * nf];
-                Fo[v] = to[((long)(M + v) * E) * nf];
-                Un[v] = tn[((long)v * E) * nf];
-                Fn[v] = tn[((long)(M + v) * E) * nf];
-                unn[v] = uin[((long)v * E + en) * NP + nnode];
-            }
-            real ndn[NF];
-            Phys::node_basic(unn, ndn, ctx);
-            const real lam = dmax(Phys::speed(d, ndo, ctx), Phys::speed(d, ndn, ctx));
-            const real *UL = side ? Uo : Un, *UR = side ? Un : Uo;
-            const real *FL = side ? Fo : Fn, *FR = side ? Fn : Fo;
-            real Fs[M];
-#pragma unroll
-            for (int v = 0; v < M; ++v) Fs[v] = real(0.5) * (FL[v] + FR[v]) - real(0.5) * lam * (UR[v] - UL[v]);
-            if (blend) {
-                const real aface = real(0.5) * (alpha_e + real(a.alpha[en]));
-                if (aface > real(0)) {
-                    real fo[M], fn[M];
-                    Phys::phys(d, ndo, fo, ctx);
-                    Phys::phys(d, ndn, fn, ctx);
-                    const real *fL = side ? fo : fn, *fR = side ? fn : fo;
-                    const real *uL = side ? uno : unn, *uR = side ? unn : uno;
-#pragma unroll
-                    for (int v = 0; v < M; ++v) {
-                        const real flo = real(0.5) * (fL[v] + fR[v]) - real(0.5) * lam * (uR[v] - uL[v]);
-                        Fs[v] = (real(1) - aface) * Fs[v] + aface * flo;
-                    }
-                }
-            }
+            const real *tn = tr + ((long)nface * FD::NCT * E + en) * nf + kk;
             real jump[M];
 #pragma unroll
-            for (int v = 0; v < M; ++v) jump[v] = Fs[v] - (real(1) - alpha_e) * Fo[v];
+            for (int v = 0; v < M; ++v) jump[v] = tn[((long)v * E) * nf];
             if constexpr (EQ == EQ_MHD) {
                 real o[M];
-                MhdP<real, FLUX>::btimes(d, ndo, real(0.5) * (UL[5 + d] + UR[5 + d]), real(0.5) * (UL[8] + UR[8]), o);
+                MhdP<real, FLUX>::btimes(d, ndo, real(0.5) * tn[((long)M * E) * nf],
+                                         real(0.5) * tn[((long)(M + 1) * E) * nf], o);
 #pragma unroll
                 for (int v = 0; v < M; ++v) jump[v] += o[v];
             }
-            const real coef = rdt * real(t.invw_dx[d][0]);
+            const real coef = rdt * real(t.invw_dx[d][side ? N : 0]);
 #pragma unroll
             for (int v = 0; v < M; ++v) u[v] += side ? -coef * jump[v] : coef * jump[v];
         }
@@ -623,15 +750,22 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
     }
     if (!tail) return;
 
-    // pipelined tail: CFL maximum and raw indicator of u^{n+1}
+    // pipelined tail: CFL maximum, face wave speeds and raw indicator of u^{n+1}
     real nd[NF];
     Phys::node_basic(u, nd, ctx);
     double sp = 0.0;
     if (valid) {
+        real *ts = (real *)a.traces;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            if constexpr (EQ == EQ_MHD) sp = fmax(sp, (double)MhdP<real, FLUX>::fast(d, nd, ctx));
-            else sp += (double)Phys::speed(d, nd, ctx) * t.invdx[d];
+            const real sd = face_speed<real, EQ, DIM, FLUX>(d, nd, ctx);
+            if constexpr (EQ == EQ_MHD) sp = fmax(sp, (double)sd);
+            else sp += (double)sd * t.invdx[d];
+            if (pd[d] == 0 || pd[d] == N) {
+                const int face = 2 * d + (pd[d] == N ? 1 : 0);
+                const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
+                ts[((long)(face * FD::NCT + FD::SPEED) * E + e) * nf + kk] = sd;
+            }
         }
     }
     if constexpr (EQ == EQ_EULER) {
@@ -748,9 +882,10 @@ static __global__ void __launch_bounds__(BLOCK) k_smooth(const Tables t, const d
 {
     const long e = (long)blockIdx.x * BLOCK + threadIdx.x;
     if (e >= t.nelem) return;
+    const Nbrs nb = neighbours(t, e);
     double a = alpha_raw[e];
     for (int d = 0; d < t.dim; ++d)
-        for (int s = 0; s < 2; ++s) a = fmax(a, 0.5 * alpha_raw[neighbour(t, e, d, s)]);
+        for (int s = 0; s < 2; ++s) a = fmax(a, 0.5 * alpha_raw[s ? nb.n[d][1] : nb.n[d][0]]);
     alpha[e] = a;
 }
 
@@ -867,6 +1002,16 @@ hipError_t launch_interface(const Tables &t, const StepPtrs &p, hipStream_t s)
     if (p.dt_out != nullptr)
         hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(BLOCK), 0, s, t, (const double *)p.partials, grid,
                            EQ == EQ_MHD ? 1 : 0, p.dt_out);
+    return hipGetLastError();
+}
+
+template <typename real, int EQ, int DIM, int N, int FLUX>
+hipError_t launch_face_speed(const Tables &t, const StepPtrs &p, hipStream_t s)
+{
+    constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
+    constexpr int EPB = BLOCK / NP;
+    const int grid = (t.nelem + EPB - 1) / EPB;
+    hipLaunchKernelGGL((k_face_speed<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(BLOCK), 0, s, t, p.u_in, p.traces);
     return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ def generate(seeds, n=128, t_snaps=(1.0, 1.5, 2.0, 2.5, 3.0), frac=1.0, sample_s
             f = crk.features(s, cur)
             s.step(cur, uh, dt_h, alpha=zero_alpha, compute_dt=True)
             lab = crk.labels(s, cur, uh, tol=tol)
+            s.prepare(cur, dt)              # the full step used the pipeline's workspace
             keep = torch.tensor(rng.permutation(s.nelem)[: int(frac * s.nelem)], device="cuda")
             X.append(f[keep])
             Y.append(lab[keep])

@@ -93,27 +93,71 @@ def test_dt_parity(orc, dim, N, vol):
     assert abs(dt[0] - orc.compute_dt(p, u)) <= 1e-14 * dt[0]
 
 
-def test_traces_parity(orc):
-    """Local phase alone: U and F traces of every face node against the oracle."""
-    p, s = _pair(orc, dim=2, nx=9, ny=7, N=3, vol_flux=2)
+def _face_neighbour(p, e, d, side):
+    ex, ey = e % p.nx, e // p.nx
+    if d == 0:
+        ex = (ex + (1 if side else -1)) % p.nx
+    else:
+        ey = (ey + (1 if side else -1)) % p.ny
+    return ey * p.nx + ex
+
+
+@pytest.mark.parametrize("blend", [False, True])
+def test_face_data_parity(orc, blend):
+    """Local phase alone.  The shares the two elements of a face publish sum
+    to the oracle's interface flux at every face node; interior nodes hold
+    u^n - dt V; face nodes add the own lifted share minus (1-alpha) F."""
+    kw = dict(x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, limiter=orc.LIM_BLEND_GIVEN) if blend else {}
+    p, s = _pair(orc, dim=2, nx=9, ny=7, N=3, vol_flux=2, **kw)
     u = _state(orc, p, seed=5)
     dt = orc.compute_dt(p, u)
+    alpha = None
+    if blend:
+        alpha = np.random.default_rng(8).uniform(0.0, 0.008, p.nelem)
+        alpha[::3] = 0.0
     V, Ut, Ft, _ = orc.local_phase(p, u, dt)
+    Fs = orc.face_fluxes(p, u, dt, alpha)                  # [e, face, k, v]
     ug = torch.tensor(u, device="cuda")
     out, tr = s.new_state(), s.new_traces()
-    s.local_stages(ug, torch.tensor([dt, 0.0], device="cuda", dtype=torch.float64), out, tr)
+    al = None if alpha is None else torch.tensor(alpha, device="cuda")
+    s.local_stages(ug, torch.tensor([dt, 0.0], device="cuda", dtype=torch.float64), out, tr, alpha=al)
     torch.cuda.synchronize()
-    T = s.trace_view(tr).cpu().numpy()              # [face, c, e, k]
-    M = p.nvar
-    for face in range(4):
-        gU = T[face, :M].transpose(1, 2, 0)           # [e, k, v]
-        gF = T[face, M:2 * M].transpose(1, 2, 0)
-        assert np.max(np.abs(gU - Ut[:, face])) <= 1e-13 * np.max(np.abs(Ut))
-        assert np.max(np.abs(gF - Ft[:, face])) <= 1e-13 * np.max(np.abs(Ft))
-    # provisional state of the interior nodes is u^n - dt V exactly there
-    interior = [5, 6, 9, 10]
-    got = out.cpu().numpy()[:, :, interior]
-    assert _rel(got, (u - dt * V)[:, :, interior]) <= TOL64
+    T = s.trace_view(tr).cpu().numpy()
+    P = T[:, :p.nvar].transpose(2, 0, 3, 1)                  # [e, face, k, v]
+    M, N = p.nvar, p.N
+    # last component: wave speed of u^n in the face's direction at its nodes
+    for e in (0, 17, p.nelem - 1):
+        for face in range(4):
+            d, side = divmod(face, 2)
+            for k in range(N + 1):
+                node = (N * side if d == 0 else k) + (N + 1) * (k if d == 0 else N * side)
+                ref = orc.wave_speed(p, d, u[:, e, node])
+                assert abs(T[face, -1, e, k] - ref) <= 1e-14 * ref
+    got = out.cpu().numpy()
+    pre = np.zeros_like(u)
+    w = orc.gll(N)[1]
+    dx = [(p.x1 - p.x0) / p.nx, (p.y1 - p.y0) / p.ny]
+    a = np.zeros(p.nelem) if alpha is None else alpha
+    scale = np.max(np.abs(Fs))
+    for e in range(p.nelem):
+        for d in range(2):
+            for side in range(2):
+                face, en = 2 * d + side, _face_neighbour(p, e, d, side)
+                both = P[e, face] + P[en, 2 * d + 1 - side]
+                assert np.max(np.abs(both - Fs[e, face])) <= 1e-13 * scale
+                for k in range(N + 1):
+                    node = (N * side if d == 0 else k) + (N + 1) * (k if d == 0 else N * side)
+                    c = dt / (w[N if side else 0] * dx[d]) * (-1.0 if side else 1.0)
+                    pre[:, e, node] += c * (P[e, face, k] - (1.0 - a[e]) * Ft[e, face, k])
+    if not blend:                                   # (the oracle has no separate subcell update)
+        ref = u - dt * V + pre
+        assert _rel(got[:, :, [5, 6, 9, 10]], ref[:, :, [5, 6, 9, 10]]) <= TOL64
+        assert _rel(got, ref) <= TOL64
+    # the interface phase completes the step
+    s.interface_update(ug, tr, torch.tensor([dt, 0.0], device="cuda", dtype=torch.float64), out)
+    torch.cuda.synchronize()
+    ref, _ = orc.crk_step(p, u, dt, alpha)
+    assert _rel(out.cpu().numpy(), ref) <= TOL64
 
 
 def test_blending_parity_khi(orc):

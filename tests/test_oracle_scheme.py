@@ -355,6 +355,61 @@ def test_blending_alpha_one_is_subcell_fv(orc, dim):
     assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(u))
 
 
+def _facing(prob, e, d, side):
+    ex, ey = e % prob.nx, e // prob.nx
+    if prob.dim == 1:
+        return (e + (1 if side else -1)) % prob.nx
+    if d == 0:
+        ex = (ex + (1 if side else -1)) % prob.nx
+    else:
+        ey = (ey + (1 if side else -1)) % prob.ny
+    return ey * prob.nx + ex
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_face_fluxes(orc, dim):
+    """The interface flux is one value per face (identical seen from both
+    elements), equals f(u) for a constant state, and with alpha = 1 is the
+    first-order Rusanov flux of the u^n traces whatever the time averages."""
+    xi, _ = orc.gll(3)
+    prob = orc.Problem(dim=dim, N=3, nx=5, ny=4, vol_flux=orc.VOL_RANOCHA, limiter=orc.LIM_BLEND_GIVEN)
+    u = inputs.random_smooth_euler(5, 4, xi, seed=4, dim=dim, amp=0.3)
+    dt = orc.compute_dt(prob, u)
+    alpha = np.random.default_rng(3).uniform(0, 0.5, prob.nelem)
+    F = orc.face_fluxes(prob, u, dt, alpha)
+    nf = F.shape[2]
+    for e in range(prob.nelem):
+        for d in range(dim):
+            for side in range(2):
+                en = _facing(prob, e, d, side)
+                assert np.array_equal(F[e, 2 * d + side], F[en, 2 * d + 1 - side])
+    # constant state
+    uc = _const_state(prob, np.random.default_rng(5))
+    Fc = orc.face_fluxes(prob, uc, dt, alpha)
+    for d in range(dim):
+        fc = orc.phys_flux(prob, d, uc[:, 0, 0])
+        assert np.max(np.abs(Fc[:, 2 * d:2 * d + 2] - fc)) < 1e-14 * np.max(np.abs(fc))
+    # alpha = 1: Rusanov flux of u^n, independent of dt
+    F1 = orc.face_fluxes(prob, u, dt, np.ones(prob.nelem))
+    F2 = orc.face_fluxes(prob, u, 0.3 * dt, np.ones(prob.nelem))
+    assert np.max(np.abs(F1 - F2)) < 1e-14 * np.max(np.abs(F1))
+    n = prob.N + 1
+    for e in (0, prob.nelem - 1):
+        for d in range(dim):
+            for k in range(nf):
+                # left face of element e: left state from the neighbour's last node
+                en = _facing(prob, e, d, 0)
+                if dim == 1:
+                    pl, pr = n - 1, 0
+                else:
+                    pl = (n - 1) + n * k if d == 0 else k + n * (n - 1)
+                    pr = n * k if d == 0 else k
+                uL, uR = u[:, en, pl], u[:, e, pr]
+                lam = max(orc.wave_speed(prob, d, uL), orc.wave_speed(prob, d, uR))
+                ref = 0.5 * (orc.phys_flux(prob, d, uL) + orc.phys_flux(prob, d, uR)) - 0.5 * lam * (uR - uL)
+                assert np.max(np.abs(F1[e, 2 * d, k] - ref)) < 1e-14 * np.max(np.abs(ref))
+
+
 def _modal_state(orc, N, modes, rho=None):
     """eps = rho p at the nodes from given orthonormal Legendre coefficients
     m[l, k] (numpy's Legendre module, independent of the oracle)."""
