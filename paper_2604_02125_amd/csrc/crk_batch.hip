@@ -116,7 +116,16 @@ __global__ void __launch_bounds__(256) k_batch_dt(const BatchProblem *probs, con
     __shared__ double red[256];
     const BatchProblem &bp = probs[blockIdx.x];
     double m = 0.0;
-    for (int k = threadIdx.x; k < bp.ntiles; k += 256) m = fmax(m, partials[bp.tile0 + k]);
+    for (int k0 = 0; k0 < bp.ntiles; k0 += 4 * 256) {
+        double v[4];              // independent loads in flight together
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + j * 256 + threadIdx.x;
+            v[j] = k < bp.ntiles ? partials[bp.tile0 + k] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) m = fmax(m, v[j]);
+    }
     red[threadIdx.x] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {

@@ -61,11 +61,12 @@ struct StepPtrs {
 struct Nbrs {
     long n[2][2];   // [d][side]
 };
+template <int DIM>
 __device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
 {
     Nbrs r;
     const int nx = t.nx, ei = (int)e;
-    if (t.dim == 1) {
+    if constexpr (DIM == 1) {
         r.n[0][0] = ei == 0 ? nx - 1 : ei - 1;
         r.n[0][1] = ei + 1 == nx ? 0 : ei + 1;
         r.n[1][0] = r.n[1][1] = e;
@@ -81,6 +82,10 @@ __device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
     r.n[1][0] = (ey == 0 ? (t.ny - 1) * nx : row - nx) + ex;
     r.n[1][1] = (ey + 1 == t.ny ? 0 : row + nx) + ex;
     return r;
+}
+__device__ __forceinline__ Nbrs neighbours_any(const Tables &t, long e)
+{
+    return t.dim == 1 ? neighbours<1>(t, e) : neighbours<2>(t, e);
 }
 
 template <typename real, int EQ, int DIM, int FLUX> struct PhysOf;
@@ -287,7 +292,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         onface[d] = (pd[d] == 0) || (pd[d] == N);
         side[d] = (pd[d] == N) ? 1 : 0;
     }
-    const Nbrs nb = neighbours(t, es);
+    const Nbrs nb = neighbours<DIM>(t, es);
 
     // Rusanov speed of each face through this node: lambda = max of the
     // wave speeds of u^n on both sides (eq:numflux.cons; MHD: and c_h), from
@@ -339,7 +344,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                     for (int sd = 0; sd < 2; ++sd) am = fmax(am, 0.5 * a.alpha_raw[nb.n[d][sd]]);
                 a.alpha_s[e] = am;
             } else {
-                const Nbrs nt = neighbours(t, tg);
+                const Nbrs nt = neighbours<DIM>(t, tg);
                 am = a.alpha_raw[tg];
 #pragma unroll
                 for (int d = 0; d < DIM; ++d)
@@ -350,17 +355,42 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         }
     }
 
+    // Interface flux, split by side.  With lambda and the face blending
+    // factor a known to both elements, the blended Rusanov flux of
+    // eq:numflux.cons is F* = P^- + P^+ with
+    //   P^- = (1-a)(F^-/2 + lambda U^-/2) + a(f(u^-)/2 + lambda u^-/2)
+    //   P^+ = (1-a)(F^+/2 - lambda U^+/2) + a(f(u^+)/2 - lambda u^+/2)
+    // (U = sum_i b_i u^(i), F = sum_i b_i f_d(u^(i)) at the face node, u = u^n).
+    // The element applies its own share and its own trace term
+    // -(1-alpha_e) F of the lifting itself and publishes P for the neighbour.
+    // Nothing needs U or F on their own, so each stage adds its terms
+    // straight into P (per face direction) and into W, where
+    //   u_out = u^n - dt W,
+    //   W = (1-alpha_e) sum_i b_i R^(i) + alpha_e L
+    //       - sum_d s_d/(w dx_d) [P_d - (1-alpha_e) F_d]   (s_d = +1 at xi_d = 0, -1 at xi_d = 1)
+    // (L: interior subcell FV update).  For MHD the own non-conservative
+    // trace term and the own half of 1/2 B(u^n)(g(U^-) + g(U^+)) enter W the
+    // same way; the normal field and psi of U are kept and published.
     real Z[S][M];     // Z[k] = sum_{j<k} a_kj R^(j)
-    // V accumulates (1 - alpha) sum_j b_j R^(j) + alpha L (L: interior subcell FV update)
-    real V[M], U[M], F[DIM][M], Fnc[DIM][M];
-    real oma = real(1) - alpha;
+    real W[M], P[DIM][M];
+    real UB[DIM], Upsi = real(0);   // MHD: time averages of B_d and psi
+    real hl[DIM], sw[DIM], oaf[DIM], cF[DIM], cU = real(0);
+    real oma = real(1);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-        V[v] = real(0); U[v] = real(0);
+        W[v] = real(0);
 #pragma unroll
         for (int k = 0; k < S; ++k) Z[k][v] = real(0);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) { F[d][v] = real(0); Fnc[d][v] = real(0); }
+        for (int d = 0; d < DIM; ++d) P[d][v] = real(0);
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        UB[d] = real(0);
+        sw[d] = onface[d] ? (side[d] ? -invw[d] : invw[d]) : real(0);
+        hl[d] = onface[d] ? (side[d] ? real(0.5) : real(-0.5)) * llds[d * BLK + tid] : real(0);
+        oaf[d] = real(1);
+        cF[d] = real(0);
     }
 
 #pragma unroll
@@ -368,21 +398,53 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         real us[M];
 #pragma unroll
         for (int v = 0; v < M; ++v) us[v] = (i == 0) ? un[v] : un[v] - rdt * Z[i][v];
+        const real bi = real(t.b[i]);
+        if (i > 0) {
+            // the u^(i) terms of P_d and W (those of u^(0) = u^n follow the
+            // first barrier, where the blending factors are known)
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                const real g = oaf[d] * bi * hl[d];
+#pragma unroll
+                for (int v = 0; v < M; ++v) P[d][v] += g * us[v];
+            }
+            const real c = bi * cU;
+#pragma unroll
+            for (int v = 0; v < M; ++v) W[v] -= c * us[v];
+        }
+        if constexpr (EQ == EQ_MHD) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) UB[d] += bi * us[5 + d];
+            Upsi += bi * us[8];
+        }
         real nd[NF];
         Phys::node(us, nd, ctx);
         if (i > 0) element_sync<NP>();    // the previous stage has finished reading LDS
 #pragma unroll
         for (int f = 0; f < NF; ++f) lds[f * BLK + tid] = nd[f];
         element_sync<NP>();
-        if (i == 0 && blend && valid) {
-            alpha = alds[le * NA];
+        if (i == 0) {
+            if (blend && valid) alpha = alds[le * NA];
             oma = real(1) - alpha;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                const real af = (blend && valid && onface[d])
+                                    ? real(0.5) * (alpha + alds[le * NA + 1 + 2 * d + side[d]]) : real(0);
+                oaf[d] = real(1) - af;
+                cF[d] = sw[d] * (real(0.5) * oaf[d] - oma);
+                cU += sw[d] * oaf[d] * hl[d];
+                const real g = oaf[d] * bi * hl[d];
+#pragma unroll
+                for (int v = 0; v < M; ++v) P[d][v] += g * un[v];
+            }
+            const real c = bi * cU;
+#pragma unroll
+            for (int v = 0; v < M; ++v) W[v] -= c * un[v];
         }
 
         real R[M];
 #pragma unroll
         for (int v = 0; v < M; ++v) R[v] = real(0);
-        const real bi = real(t.b[i]);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             // directly evaluated rotations
@@ -408,20 +470,34 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                 }
             }
             // diagonal term 2 D_pp f_d(u_p) (non-zero only at the two ends of
-            // the line) and the face traces in the same branch
+            // the line) and the face terms in the same branch
             if (onface[d]) {
                 real fp[M];
                 Phys::phys(d, nd, fp, ctx);
+                const real gp = oaf[d] * bi * real(0.5), gw = bi * cF[d];
 #pragma unroll
                 for (int v = 0; v < M; ++v) {
                     R[v] += Ddiag[d] * fp[v];
-                    F[d][v] += bi * fp[v];
+                    P[d][v] += gp * fp[v];
+                    W[v] -= gw * fp[v];
+                }
+                if (i == 0 && oaf[d] < real(1)) {
+                    // first-order share a (f(u^n)/2 +- lambda u^n/2) of the blended flux
+                    const real af = real(1) - oaf[d];
+#pragma unroll
+                    for (int v = 0; v < M; ++v) {
+                        const real lo = af * (real(0.5) * fp[v] + hl[d] * un[v]);
+                        P[d][v] += lo;
+                        W[v] -= sw[d] * lo;
+                    }
                 }
                 if constexpr (EQ == EQ_MHD) {
+                    // own non-conservative trace term, b_i B_d(u^(i)) g_d(u^(i))
                     real o[M];
                     MhdP<real, FLUX>::btimes(d, nd, nd[5 + d], nd[8], o);
+                    const real go = bi * sw[d];
 #pragma unroll
-                    for (int v = 0; v < M; ++v) Fnc[d][v] += bi * o[v];
+                    for (int v = 0; v < M; ++v) W[v] += go * o[v];
                 }
             }
             if constexpr (EQ == EQ_MHD) {
@@ -463,7 +539,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                     }
                 }
 #pragma unroll
-                for (int v = 0; v < M; ++v) V[v] += alpha * invw[d] * (fr[v] - fl[v]);
+                for (int v = 0; v < M; ++v) W[v] += alpha * invw[d] * (fr[v] - fl[v]);
             }
         }
         if constexpr (SYM) {
@@ -499,75 +575,41 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         }
         const real wbi = oma * bi;
 #pragma unroll
-        for (int v = 0; v < M; ++v) {
-            V[v] += wbi * R[v];
-            U[v] += bi * us[v];
-        }
+        for (int v = 0; v < M; ++v) W[v] += wbi * R[v];
     }
 
     if (!valid) return;
-    real res[M];
+    if constexpr (EQ == EQ_MHD) {
+        // own half of 1/2 B(u^n)(g(U^-) + g(U^+))
+        real ndo[NF];
+        Phys::node_basic(un, ndo, ctx);
 #pragma unroll
-    for (int v = 0; v < M; ++v) res[v] = un[v] - rdt * V[v];
-
-    // Interface flux, split by side.  With lambda and the face blending
-    // factor a known to both elements, the blended Rusanov flux of
-    // eq:numflux.cons is F* = P^- + P^+ with
-    //   P^- = (1-a)(F^-/2 + lambda U^-/2) + a(f(u^-)/2 + lambda u^-/2)
-    //   P^+ = (1-a)(F^+/2 - lambda U^+/2) + a(f(u^+)/2 - lambda u^+/2)
-    // (U, F: time averages at the face node, u: u^n).  The element applies
-    // its own share and its own trace term -(1-alpha_e) F of the lifting
-    // here and publishes P for the neighbour; for MHD it also applies the
-    // own half of 1/2 B(u^n)(g(U^-) + g(U^+)) and publishes g(U) (the normal
-    // field and psi).  traces[face][c][e][k], c < M: P; MHD: c = M, M + 1.
+        for (int d = 0; d < DIM; ++d) {
+            if (!onface[d]) continue;
+            real o[M];
+            MhdP<real, FLUX>::btimes(d, ndo, real(0.5) * UB[d], real(0.5) * Upsi, o);
+#pragma unroll
+            for (int v = 0; v < M; ++v) W[v] -= sw[d] * o[v];
+        }
+    }
+    // face data: P for the neighbours (traces[face][c][e][k], c < M; MHD: c = M, M + 1 the normal field and psi)
     real *tr = (real *)a.traces;
-    real ndo[NF], fo[M];
-    bool have_fo = false;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         if (!onface[d]) continue;
-        const real lam = llds[d * BLK + tid];
-        const real hl = side[d] ? real(0.5) * lam : real(-0.5) * lam;
-        const real af = blend ? real(0.5) * (alds[le * NA] + alds[le * NA + 1 + 2 * d + side[d]]) : real(0);
-        const real oaf = real(1) - af;
-        real P[M];
-#pragma unroll
-        for (int v = 0; v < M; ++v) P[v] = oaf * (real(0.5) * F[d][v] + hl * U[v]);
-        if (af > real(0)) {
-            if (!have_fo) {
-                real uc[M];
-#pragma unroll
-                for (int v = 0; v < M; ++v) { uc[v] = un[v]; asm volatile("" : "+v"(uc[v])); }
-                Phys::node_basic(uc, ndo, ctx);
-                have_fo = true;
-            }
-            Phys::phys(d, ndo, fo, ctx);
-#pragma unroll
-            for (int v = 0; v < M; ++v) P[v] += af * (real(0.5) * fo[v] + hl * un[v]);
-        }
-        const real coef = side[d] ? -rdt * invw[d] : rdt * invw[d];
-#pragma unroll
-        for (int v = 0; v < M; ++v) res[v] += coef * (P[v] - oma * F[d][v]);
-        if constexpr (EQ == EQ_MHD) {
-            if (!have_fo) { Phys::node_basic(un, ndo, ctx); have_fo = true; }
-            real o[M];
-            MhdP<real, FLUX>::btimes(d, ndo, real(0.5) * U[5 + d], real(0.5) * U[8], o);
-#pragma unroll
-            for (int v = 0; v < M; ++v) res[v] += coef * (o[v] - Fnc[d][v]);
-        }
         const int face = 2 * d + side[d];
         const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
         real *tb = tr + ((long)face * FD::NCT * E + e) * nfn + kk;
 #pragma unroll
-        for (int v = 0; v < M; ++v) tb[((long)v * E) * nfn] = P[v];
+        for (int v = 0; v < M; ++v) tb[((long)v * E) * nfn] = P[d][v];
         if constexpr (EQ == EQ_MHD) {
-            tb[((long)M * E) * nfn] = U[5 + d];
-            tb[((long)(M + 1) * E) * nfn] = U[8];
+            tb[((long)M * E) * nfn] = UB[d];
+            tb[((long)(M + 1) * E) * nfn] = Upsi;
         }
     }
     real *uout = (real *)a.u_out;
 #pragma unroll
-    for (int v = 0; v < M; ++v) uout[((long)v * E + e) * NP + node] = res[v];
+    for (int v = 0; v < M; ++v) uout[((long)v * E + e) * NP + node] = un[v] - rdt * W[v];
 }
 
 template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB = 0>
@@ -583,6 +625,16 @@ __global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs 
 // per node: modal coefficients in the orthonormal Legendre basis, energy in
 // the highest modes, logistic map (Hennemann-Gassner form), clipping at
 // alpha_min and cap at alpha_max.  Every lane of the workgroup must call it.
+// sum over the aligned groups of W consecutive lanes of a wavefront (W a
+// power of two dividing 64); every lane of a group gets the same bits
+template <int W>
+__device__ __forceinline__ double group_sum(double x)
+{
+#pragma unroll
+    for (int m = 1; m < W; m <<= 1) x += __shfl_xor(x, m, W);
+    return x;
+}
+
 template <int DIM, int N, int BLK>
 __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le, int node, long e, bool valid,
                                                 double eps_node, double *eps, double *en, double *alpha_raw,
@@ -590,20 +642,17 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
 {
     constexpr int n1 = N + 1;
     constexpr int NP = DIM == 2 ? n1 * n1 : n1;
+    // an element's lanes are one aligned power-of-two group of a wavefront:
+    // exchange and sums stay inside the wavefront
+    constexpr bool WAVE = (NP & (NP - 1)) == 0 && 64 % NP == 0;
     eps[tid] = eps_node;
-    __syncthreads();
+    element_sync<NP>();
     const int mk = node % n1, ml = DIM == 2 ? node / n1 : 0;
     double rk[n1], rl[n1];
 #pragma unroll
     for (int c = 0; c < n1; ++c) {
-        double x = 0.0, y = 0.0;
-#pragma unroll
-        for (int r = 0; r < n1; ++r) {
-            if (mk == r) x = t.Vinv[r][c];
-            if (ml == r) y = t.Vinv[r][c];
-        }
-        rk[c] = x;
-        rl[c] = y;
+        rk[c] = t.Vinv[mk][c];
+        rl[c] = t.Vinv[ml][c];
     }
     double m = 0.0;
     if constexpr (DIM == 1) {
@@ -619,17 +668,28 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
         }
     }
     const double e2 = m * m;
-    en[tid] = e2;
-    en[BLK + tid] = (mk <= N - 1 && ml <= N - 1) ? e2 : 0.0;
-    en[2 * BLK + tid] = (mk <= N - 2 && ml <= N - 2) ? e2 : 0.0;
-    __syncthreads();
-    if (valid && node == 0) {
-        double tot = 0.0, c1 = 0.0, c2 = 0.0;
-        for (int p = 0; p < NP; ++p) {
-            tot += en[le * NP + p];
-            c1 += en[BLK + le * NP + p];
-            c2 += en[2 * BLK + le * NP + p];
+    const double x1 = (mk <= N - 1 && ml <= N - 1) ? e2 : 0.0;
+    const double x2 = (mk <= N - 2 && ml <= N - 2) ? e2 : 0.0;
+    double tot, c1, c2;
+    if constexpr (WAVE) {
+        tot = group_sum<NP>(e2);
+        c1 = group_sum<NP>(x1);
+        c2 = group_sum<NP>(x2);
+    } else {
+        en[tid] = e2;
+        en[BLK + tid] = x1;
+        en[2 * BLK + tid] = x2;
+        __syncthreads();
+        tot = c1 = c2 = 0.0;
+        if (valid) {
+            for (int p = 0; p < NP; ++p) {
+                tot += en[le * NP + p];
+                c1 += en[BLK + le * NP + p];
+                c2 += en[2 * BLK + le * NP + p];
+            }
         }
+    }
+    if (valid && node == 0) {
         const double E1 = (tot - c1) / tot, E2 = (c1 - c2) / c1;
         const double En = E1 > E2 ? E1 : E2;
         double al = 1.0 / (1.0 + exp(-(t.ind_sharpness / t.ind_threshold) * (En - t.ind_threshold)));
@@ -640,11 +700,8 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
     }
     // features of the learned indicator: the modal energy fractions
     // f = m_kl^2 / sum m^2 on a log scale, 1 + log10(max(f, 1e-16))/16 in [0, 1]
-    if (features != nullptr && valid) {
-        double tot = 0.0;
-        for (int p = 0; p < NP; ++p) tot += en[le * NP + p];
+    if (features != nullptr && valid)
         features[e * NP + node] = (float)(1.0 + log10(fmax(e2 / tot, 1e-16)) / 16.0);
-    }
 }
 
 // Workgroup maximum of v (all lanes call) into partials[blockIdx.x]; a
@@ -652,14 +709,19 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
 template <int BLK>
 __device__ __forceinline__ void block_max_lanes(double v, double *red, double *slot)
 {
+    // maximum over the wavefront by butterfly, then over the BLK/64 wavefronts
+    static_assert(BLK % 64 == 0, "whole wavefronts");
     const int tid = threadIdx.x;
-    red[tid] = v;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
-    for (int w = BLK / 2; w > 0; w >>= 1) {
-        if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
-        __syncthreads();
+    if (tid == 0) {
+        double r = red[0];
+#pragma unroll
+        for (int w = 1; w < BLK / 64; ++w) r = fmax(r, red[w]);
+        *slot = r;
     }
-    if (tid == 0) *slot = red[0];
 }
 
 // ---------------------------------------------------------------- K3: interface + final update
@@ -714,7 +776,7 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
         // the neighbour's share of the interface flux (the own share and the
         // own trace term were applied by the local phase), lifted with
         // dg_R/dxi = delta_pN/w_N, dg_L/dxi = -delta_p0/w_0
-        const Nbrs nb = neighbours(t, e);
+        const Nbrs nb = neighbours<DIM>(t, e);
         real ndo[NF];
         if constexpr (EQ == EQ_MHD) {
             const real *uin = (const real *)a.u_in;
@@ -822,20 +884,33 @@ __global__ void __launch_bounds__(BLOCK) k_dt_partial(const Tables t, const void
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-static __global__ void __launch_bounds__(BLOCK) k_dt_final(const Tables t, const double *partials, int nparts, int is_mhd,
-                                                            double *dt)
+constexpr int FINAL_BLOCK = 1024;
+static __global__ void __launch_bounds__(FINAL_BLOCK) k_dt_final(const Tables t, const double *partials, int nparts,
+                                                                 int is_mhd, double *dt)
 {
-    __shared__ double red[BLOCK];
+    // the partials were just written by workgroups on every XCD, so each load
+    // is a round trip to memory: issue eight per lane at once rather than one
+    // after the other
+    __shared__ double red[FINAL_BLOCK / 64];
+    const int tid = threadIdx.x;
     double mx = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += BLOCK) mx = fmax(mx, partials[k]);
-    red[threadIdx.x] = mx;
-    __syncthreads();
-    for (int w = BLOCK / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
+    for (int k0 = 0; k0 < nparts; k0 += 8 * FINAL_BLOCK) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = k0 + j * FINAL_BLOCK + tid;
+            v[j] = k < nparts ? partials[k] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) mx = fmax(mx, v[j]);
     }
-    if (threadIdx.x == 0) {
-        const double m = red[0];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double m = red[0];
+        for (int w = 1; w < FINAL_BLOCK / 64; ++w) m = fmax(m, red[w]);
         if (is_mhd) {
             // every lambda_d = max(|v_d| + c_f, c_h) equals c_h = the global max
             double sdx = 0.0;
@@ -882,7 +957,7 @@ static __global__ void __launch_bounds__(BLOCK) k_smooth(const Tables t, const d
 {
     const long e = (long)blockIdx.x * BLOCK + threadIdx.x;
     if (e >= t.nelem) return;
-    const Nbrs nb = neighbours(t, e);
+    const Nbrs nb = neighbours_any(t, e);
     double a = alpha_raw[e];
     for (int d = 0; d < t.dim; ++d)
         for (int s = 0; s < 2; ++s) a = fmax(a, 0.5 * alpha_raw[s ? nb.n[d][1] : nb.n[d][0]]);
@@ -1000,7 +1075,7 @@ hipError_t launch_interface(const Tables &t, const StepPtrs &p, hipStream_t s)
     const int grid = (t.nelem + EPB - 1) / EPB;
     hipLaunchKernelGGL((k_interface<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(BLOCK), 0, s, t, p);
     if (p.dt_out != nullptr)
-        hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(BLOCK), 0, s, t, (const double *)p.partials, grid,
+        hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(FINAL_BLOCK), 0, s, t, (const double *)p.partials, grid,
                            EQ == EQ_MHD ? 1 : 0, p.dt_out);
     return hipGetLastError();
 }
@@ -1039,7 +1114,7 @@ hipError_t launch_dt(const Tables &t, const void *u, double *partials, double *d
 {
     const int g = reduction_blocks(t);
     hipLaunchKernelGGL((k_dt_partial<real, EQ, DIM>), dim3(g), dim3(BLOCK), 0, s, t, u, partials);
-    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(BLOCK), 0, s, t, (const double *)partials, g, EQ == EQ_MHD ? 1 : 0, dt);
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(FINAL_BLOCK), 0, s, t, (const double *)partials, g, EQ == EQ_MHD ? 1 : 0, dt);
     return hipGetLastError();
 }
 

@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(BLOCK) k_labels(const Tables t, const void *un
         const double m2 = u[((long)2 * E + el) * NP + node], En = u[((long)3 * E + el) * NP + node];
         return (t.gamma - 1.0) * (En - 0.5 * (m1 * m1 + m2 * m2) / r);
     };
-    const Nbrs nb = neighbours(t, es);
+    const Nbrs nb = neighbours<2>(t, es);
     long list[5] = {es, nb.n[0][0], nb.n[0][1], nb.n[1][0], nb.n[1][1]};
     double rmin = INFINITY, rmax = -INFINITY, pmin = INFINITY, pmax = -INFINITY;
     for (int k = 0; k < 5; ++k) {
