@@ -292,7 +292,8 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     const int nc = t.M + (m->equation == CRK_GLM_MHD ? 2 : 0) + 1;
     s->trace_bytes = (size_t)2 * t.dim * nc * nelem * t.nface * s->elem_bytes;
     size_t off = 0;
-    const long elem_blocks = (nelem + (BLOCK / nnode) - 1) / (BLOCK / nnode);
+    const long epb = tile_block_rt((int)nnode) / nnode;   // elements per interface-phase workgroup
+    const long elem_blocks = (nelem + epb - 1) / epb;
     const long nparts = elem_blocks > RED_BLOCKS * 16 ? elem_blocks : RED_BLOCKS * 16;
     s->off_partials = off; off = align256(off + sizeof(double) * nparts);
     s->off_araw = off; off = align256(off + sizeof(double) * nelem);

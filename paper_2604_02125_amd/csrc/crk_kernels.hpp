@@ -17,6 +17,15 @@ constexpr int MAXN = 4;      // highest compiled degree
 constexpr int MAXS = 6;      // highest stage count
 constexpr int BLOCK = 256;   // lanes per workgroup of the element kernels
 constexpr int RED_BLOCKS = 1024;  // max workgroups of the reduction kernels
+#ifndef CRK_WAVE_TILE
+#define CRK_WAVE_TILE 64
+#endif
+// Workgroup of the local-stage and interface kernels for elements of NP
+// nodes: when whole elements fit a wavefront those kernels need no
+// workgroup barrier, and smaller workgroups finish the grid more evenly.
+template <int NP>
+constexpr int tile_block() { return 64 % NP == 0 ? CRK_WAVE_TILE : BLOCK; }
+inline int tile_block_rt(int np) { return 64 % np == 0 ? CRK_WAVE_TILE : BLOCK; }
 
 // Everything a kernel needs besides its pointers; passed by value.
 struct Tables {
@@ -613,11 +622,12 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 }
 
 template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB = 0>
-__global__ void __launch_bounds__(BLOCK) k_local(const Tables t, const StepPtrs a)
+__global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 1>()) k_local(const Tables t, const StepPtrs a)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
-    __shared__ real smem[LocalShape<real, EQ, DIM, N, FLUX>::slots * BLOCK];
-    local_tile<real, EQ, DIM, N, FLUX, S, BLOCK, TAB>(t, a, (long)blockIdx.x * (BLOCK / NP), smem);
+    constexpr int TB = tile_block<NP>();
+    __shared__ real smem[LocalShape<real, EQ, DIM, N, FLUX>::slots * TB];
+    local_tile<real, EQ, DIM, N, FLUX, S, TB, TAB>(t, a, (long)blockIdx.x * (TB / NP), smem);
 }
 
 // ---------------------------------------------------------------- K8 helper: modal indicator
@@ -842,11 +852,12 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
 }
 
 template <typename real, int EQ, int DIM, int N, int FLUX>
-__global__ void __launch_bounds__(BLOCK) k_interface(const Tables t, const StepPtrs a)
+__global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 1>()) k_interface(const Tables t, const StepPtrs a)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
-    __shared__ double dsmem[5 * BLOCK];
-    interface_tile<real, EQ, DIM, N, FLUX, BLOCK>(t, a, (long)blockIdx.x * (BLOCK / NP), blockIdx.x, dsmem);
+    constexpr int TB = tile_block<NP>();
+    __shared__ double dsmem[5 * TB];
+    interface_tile<real, EQ, DIM, N, FLUX, TB>(t, a, (long)blockIdx.x * (TB / NP), blockIdx.x, dsmem);
 }
 
 // ---------------------------------------------------------------- K1: time step
@@ -1050,18 +1061,19 @@ template <typename real, int EQ, int DIM, int N, int FLUX>
 hipError_t launch_local(const Tables &t, const StepPtrs &p, hipStream_t s)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
-    constexpr int EPB = BLOCK / NP;
+    constexpr int TB = tile_block<NP>();
+    constexpr int EPB = TB / NP;
     const int grid = (t.nelem + EPB - 1) / EPB;
     switch (t.stages) {
-    case 1: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 1>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
-    case 2: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 2>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
-    case 3: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 3>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
+    case 1: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 1>), dim3(grid), dim3(TB), 0, s, t, p); break;
+    case 2: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 2>), dim3(grid), dim3(TB), 0, s, t, p); break;
+    case 3: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 3>), dim3(grid), dim3(TB), 0, s, t, p); break;
     case 4:
-        if (t.tableau == 1) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 1>), dim3(grid), dim3(BLOCK), 0, s, t, p);
-        else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4>), dim3(grid), dim3(BLOCK), 0, s, t, p);
+        if (t.tableau == 1) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 1>), dim3(grid), dim3(TB), 0, s, t, p);
+        else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4>), dim3(grid), dim3(TB), 0, s, t, p);
         break;
-    case 5: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 5>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
-    case 6: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6>), dim3(grid), dim3(BLOCK), 0, s, t, p); break;
+    case 5: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 5>), dim3(grid), dim3(TB), 0, s, t, p); break;
+    case 6: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6>), dim3(grid), dim3(TB), 0, s, t, p); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1071,9 +1083,10 @@ template <typename real, int EQ, int DIM, int N, int FLUX>
 hipError_t launch_interface(const Tables &t, const StepPtrs &p, hipStream_t s)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
-    constexpr int EPB = BLOCK / NP;
+    constexpr int TB = tile_block<NP>();
+    constexpr int EPB = TB / NP;
     const int grid = (t.nelem + EPB - 1) / EPB;
-    hipLaunchKernelGGL((k_interface<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(BLOCK), 0, s, t, p);
+    hipLaunchKernelGGL((k_interface<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(TB), 0, s, t, p);
     if (p.dt_out != nullptr)
         hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(FINAL_BLOCK), 0, s, t, (const double *)p.partials, grid,
                            EQ == EQ_MHD ? 1 : 0, p.dt_out);
