@@ -31,12 +31,14 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 
-# HBM bytes per launch of k_local measured by rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE, scaled by the plain-copy calibration (read x2.0, write x1.0);
-# valid only for the kernel sources whose digest is recorded with it.
+# Per launch of k_local on the KHI 256^2 FP64 workload, from rocprofv3 --pmc:
+# HBM bytes = FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB, scaled by the plain-copy
+# calibration) and FP64 FLOPs = SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes; valid only
+# for the kernel sources whose digest is recorded with them.
 MEASURED_TRAFFIC = {
-    ("khi256", "fp64"): {"sources_sha256": "e9752acc560995176e5fd6f9f738a68afc7257adb1bf16f0633f4e15363ca0f9",
-                         "bytes": (2.0 * 17253.9 + 1.0 * 98816.1) * 1024},
+    ("khi256", "fp64"): {"sources_sha256": "4a4b2fabe095b0b73527d8e53c0387ec6af2482331d1782856c733d95650e4ad",
+                         "bytes": (2.0 * 24197.2 + 1.0 * 66048.0) * 1024,
+                         "fp64_flops": 17612800.0 * 64},
 }
 KERNEL_SOURCES = ("paper_2604_02125_amd/csrc/crk_kernels.hpp", "paper_2604_02125_amd/csrc/crk_physics.hpp")
 
@@ -55,14 +57,13 @@ KHI = dict(dim=2, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, degree=3, volume_flux=1, cfl
 
 
 def k2_bytes_per_dof(M: int, dim: int, N: int, elem: int) -> float:
-    """Algorithmic HBM bytes of the local-stage kernel per DOF: read u^n,
-    write the provisional state, read u^n of the face neighbours at the
-    facing nodes and write the element's share of the interface flux (M
-    values each per face node, 2*dim faces of (N+1)^(dim-1) nodes per
-    element)."""
+    """Algorithmic HBM bytes of the local-stage kernel per DOF: read u^n and
+    write the provisional state (M values per node); per face node (2*dim
+    faces of (N+1)^(dim-1) nodes per element) read the wave speed of both
+    sides and write the element's share of the interface flux (M values)."""
     npe = (N + 1) ** dim
     face_nodes = 2 * dim * (N + 1) ** (dim - 1)
-    return elem * (2 * M + 2 * M * face_nodes / npe)
+    return elem * (2 * M + (M + 2) * face_nodes / npe)
 
 
 def rel_l2(a, b):
@@ -307,7 +308,9 @@ def main():
     kb = k2_bytes_per_dof(M, 2, 3, 8) * ndof
     achieved = kb / (k2_ms * 1e-3) / 1e9
     rec = MEASURED_TRAFFIC.get(("khi256", "fp64"))
-    traffic = rec["bytes"] if rec and rec["sources_sha256"] == sources_digest() else None
+    fresh = bool(rec) and rec["sources_sha256"] == sources_digest()
+    traffic = rec["bytes"] if fresh else None
+    fp64 = rec["fp64_flops"] / (k2_ms * 1e-3) / 1e12 if fresh else None
     out = {
         "metric": "DOF-updates/s at 1 GPU",
         "value": value,
@@ -325,7 +328,10 @@ def main():
                    "elements": E, "degree": 3, "dofs": ndof, "precision": "fp64", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_local (local stages)", "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic, "kernel_ms": k2_ms, "algorithmic_bytes_per_launch": kb},
+                     "traffic": traffic, "kernel_ms": k2_ms, "algorithmic_bytes_per_launch": kb,
+                     # counter FP64 FLOPs of the same kernel over its live duration
+                     "fp64_tflops": fp64, "fp64_peak_tflops": PEAK_FP64_TFLOPS,
+                     "fp64_frac": fp64 / PEAK_FP64_TFLOPS if fp64 is not None else None},
     }
     import oracle as orc
     if not args.no_cpu_baseline:
