@@ -87,41 +87,51 @@ class Pipelined:
         self.n = 0
         crk._check(crk.lib().crk_prepare(solver._h, crk._ptr(self.buf[0]), crk._ptr(self.dt), self.sp), "prepare")
 
-    def step(self, ev=None):
+    def step(self):
         crk, L = self.crk, self.crk.lib()
         ui, uo = self.buf[self.n % 2], self.buf[(self.n + 1) % 2]
         p = crk._ptr
-        if ev is not None:
-            ev[0].record(self.stream)
         crk._check(L.crk_advance(self.s._h, p(ui), p(uo), p(self.dt), crk.PHASE_LOCAL, self.sp), "advance/local")
-        if ev is not None:
-            ev[1].record(self.stream)
         crk._check(L.crk_advance(self.s._h, p(ui), p(uo), p(self.dt), crk.PHASE_INTERFACE, self.sp), "advance/iface")
         self.n += 1
+
+    def local_phase(self):
+        """The local phase of the next step alone (leaves the step undone)."""
+        crk, L = self.crk, self.crk.lib()
+        ui, uo = self.buf[self.n % 2], self.buf[(self.n + 1) % 2]
+        p = crk._ptr
+        crk._check(L.crk_advance(self.s._h, p(ui), p(uo), p(self.dt), crk.PHASE_LOCAL, self.sp), "advance/local")
 
     @property
     def state(self):
         return self.buf[self.n % 2]
 
 
-def timed(pipe, steps, warmup, events=False, every=4):
-    """Wall time of `steps` pipelined steps; with events, the mean duration of
-    the local-stage kernel from HIP events around it on every `every`-th step
-    of the same timed region (events on every step would add their own
-    overhead to the step time)."""
-    import numpy as np
+def timed(pipe, steps, warmup, events=False, reps=20):
+    """Wall time of `steps` pipelined steps; with events, then the mean
+    duration of the local-stage kernel from HIP events on the launch stream
+    around `reps` back-to-back local phases of the current state (the local
+    phase only reads u_in, so repeating it is the same launch each time;
+    events around single launches would add their own cost to each)."""
     import torch
     for _ in range(warmup):
         pipe.step()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           if events and k % every == 0 else None for k in range(steps)]
     t0 = time.perf_counter()
-    for k in range(steps):
-        pipe.step(evs[k])
+    for _ in range(steps):
+        pipe.step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    k2 = float(np.mean([e[0].elapsed_time(e[1]) for e in evs if e is not None])) if events else None
+    k2 = None
+    if events:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        pipe.local_phase()
+        a.record(pipe.stream)
+        for _ in range(reps):
+            pipe.local_phase()
+        b.record(pipe.stream)
+        b.synchronize()
+        k2 = a.elapsed_time(b) / reps
     return el, k2
 
 

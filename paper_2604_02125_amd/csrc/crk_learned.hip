@@ -219,25 +219,131 @@ __global__ void __launch_bounds__(256) k_to_bf16(long count, const float *x, uin
 // the training range [lo, hi] and a finite output; elsewhere the modal
 // coefficient already in alpha_raw stays.  alpha < alpha_min is cut to 0 as
 // for the modal indicator.
+// Inference for the blending coefficient on the matrix cores.  One
+// wavefront takes tiles of 16 elements and forms each layer transposed,
+// Y^T = W X^T, with v_mfma_f32_16x16x16_bf16: the BF16 weights are the exact
+// A operand, and every FP32 activation enters the B operand as the sum of
+// three BF16 parts (x = hi + mid + lo to within 2^-24 |x|), so each product
+// is exact in FP32 and the result is the FP32 network up to the summation
+// order.  16x16x16 operand layout (lane l, i = 0..3): A[l % 16][4 (l / 16) + i],
+// B[4 (l / 16) + i][l % 16], D[4 (l / 16) + i][l % 16]; a layer's D is
+// therefore already the B operand of the next layer.  The weights stay in
+// registers while the wavefront walks its tiles.
+typedef short mx_s4 __attribute__((ext_vector_type(4)));
+typedef float mx_f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf_bits(float f) { return (short)f2bf(f); }
+
+__device__ __forceinline__ void split3(const float *x, mx_s4 &h, mx_s4 &m, mx_s4 &l)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint16_t bh = f2bf(x[i]);
+        const float r1 = x[i] - bf2f(bh);
+        const uint16_t bm = f2bf(r1);
+        const float r2 = r1 - bf2f(bm);
+        h[i] = (short)bh;
+        m[i] = (short)bm;
+        l[i] = bf_bits(r2);
+    }
+}
+
+__device__ __forceinline__ mx_f4 mfma3(const mx_s4 &a, const mx_s4 &bh, const mx_s4 &bm, const mx_s4 &bl, mx_f4 acc)
+{
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bm, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bh, acc, 0, 0, 0);
+}
+
+constexpr int MX_TILE = 16;
+static_assert(NIN == 16 && HID == 64, "the tiling below is written for 16 inputs and 64 hidden units");
+
 __global__ void __launch_bounds__(256) k_mlp_alpha(const uint16_t *theta, const float *features, const float *lo,
                                                    const float *hi, long nelem, double alpha_max, double alpha_min,
                                                    double *alpha_raw)
 {
-    const long e = (long)blockIdx.x * 256 + threadIdx.x;
-    if (e >= nelem) return;
-    float xs[NIN];
-    bool inside = true;
-#pragma unroll
-    for (int c = 0; c < NIN; ++c) {
-        xs[c] = features[e * NIN + c];
-        inside &= (xs[c] >= lo[c]) && (xs[c] <= hi[c]);
-    }
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, kq = lane >> 4;
+    const long wave = ((long)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const long nwaves = ((long)gridDim.x * 256) >> 6;
+    const long ntiles = (nelem + MX_TILE - 1) / MX_TILE;
+    if (wave >= ntiles) return;                       // uniform per wavefront
     const MlpView w = mlp_view(theta);
-    const float z = mlp_z(w, xs);
-    if (!inside || !isfinite(z)) return;
-    double a = alpha_max / (1.0 + exp(-(double)z));
-    if (a < alpha_min) a = 0.0;
-    alpha_raw[e] = a;
+    // per-lane weights: A blocks of W1 (hidden 16b + col, inputs 4kq..) and
+    // W2 (out 16c + col, in 16b + 4kq ..), biases and W3 of the hidden units
+    // 16b + 4kq + i this lane holds in D
+    mx_s4 A1[4], A2[4][4];
+    float B1[4][4], B2[4][4], W3[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            A1[b][i] = (short)w.W1[(16 * b + col) * NIN + 4 * kq + i];
+            B1[b][i] = bf2f(w.b1[16 * b + 4 * kq + i]);
+            B2[b][i] = bf2f(w.b2[16 * b + 4 * kq + i]);
+            W3[b][i] = bf2f(w.W3[16 * b + 4 * kq + i]);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) A2[c][b][i] = (short)w.W2[(16 * c + col) * HID + 16 * b + 4 * kq + i];
+    }
+    const float b3 = bf2f(w.b3[0]);
+    float flo[4], fhi[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { flo[i] = lo[4 * kq + i]; fhi[i] = hi[4 * kq + i]; }
+
+    for (long tile = wave; tile < ntiles; tile += nwaves) {
+        const long e = tile * MX_TILE + col;
+        const bool ev = e < nelem;
+        float x[4];
+        bool inside = true;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            x[i] = ev ? features[e * NIN + 4 * kq + i] : 0.f;
+            inside &= (x[i] >= flo[i]) && (x[i] <= fhi[i]);
+        }
+        // the four lanes of an element (col, col + 16, col + 32, col + 48)
+        inside = inside && __shfl_xor((int)inside, 16) && __shfl_xor((int)inside, 32);
+        mx_s4 xh, xm, xl;
+        split3(x, xh, xm, xl);
+        // layer 1: H1^T block b = W1[16b.., :] X^T
+        float h1[4][4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            mx_f4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mfma3(A1[b], xh, xm, xl, acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = acc[i] + B1[b][i];
+                h1[b][i] = v > 0.f ? v : 0.f;
+            }
+        }
+        mx_s4 hh[4], hm[4], hl[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) split3(h1[b], hh[b], hm[b], hl[b]);
+        // layer 2 and the output layer's partial dot product
+        float z = 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            mx_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc = mfma3(A2[c][b], hh[b], hm[b], hl[b], acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = acc[i] + B2[c][i];
+                z = fmaf(W3[c][i], v > 0.f ? v : 0.f, z);
+            }
+        }
+        z += __shfl_xor(z, 16);
+        z += __shfl_xor(z, 32);
+        z += b3;
+        if (kq == 0 && ev && inside && isfinite(z)) {
+            double a = alpha_max / (1.0 + exp(-(double)z));
+            if (a < alpha_min) a = 0.0;
+            alpha_raw[e] = a;
+        }
+    }
 }
 
 // Troubled-element labels: the unlimited update uh leaves the range of rho or
@@ -323,7 +429,12 @@ namespace crk {
 hipError_t launch_mlp_alpha(const uint16_t *theta, const float *features, const float *lo, const float *hi, long nelem,
                             double alpha_max, double alpha_min, double *alpha_raw, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mlp_alpha, dim3(blocks(nelem, 256)), dim3(256), 0, s, theta, features, lo, hi, nelem, alpha_max,
+    // four wavefronts per workgroup, each walking tiles of 16 elements; at
+    // most two wavefronts per SIMD of the 256 CUs (the register budget)
+    const long tiles = (nelem + MX_TILE - 1) / MX_TILE;
+    long g = (tiles + 3) / 4;
+    if (g > 256 * 2) g = 256 * 2;
+    hipLaunchKernelGGL(k_mlp_alpha, dim3((unsigned)g), dim3(256), 0, s, theta, features, lo, hi, nelem, alpha_max,
                        alpha_min, alpha_raw);
     return hipGetLastError();
 }
