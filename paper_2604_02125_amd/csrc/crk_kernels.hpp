@@ -178,13 +178,13 @@ __global__ void __launch_bounds__(BLOCK) k_face_speed(const Tables t, const void
 // ---------------------------------------------------------------- K2: local stages
 // For every element: S inner stages u^(i) = u^n - dt sum_{j<i} a_ij R^(j)
 // with R^(i)_p = sum_d 1/dx_d sum_q [2 D_pq f_S,d(u_p,u_q) + D_pq B_d(u_p) g_d(u_q)]
-// (eq:crkfr.inner with the volume terms of Section 3); V = sum_j b_j R^(j);
-// face traces U, F; provisional update u* (see crk_local_stages).
+// (eq:crkfr.inner with the volume terms of Section 3), the element's share
+// of the interface flux and the provisional update (see crk_local_stages).
 //
 // Pairs along a line are visited by rotation: lane p pairs with
 // q = (p + k) mod (N+1), k = 1..N.  Rotation k and N+1-k visit the same
-// unordered pairs, so for Euler each lane evaluates only the rotations
-// k < (N+1)/2 (and k = (N+1)/2 when N+1 is even) and takes the mirrored
+// unordered pairs, so each lane evaluates only the rotations k < (N+1)/2
+// (and k = (N+1)/2 when N+1 is even) and takes the mirrored symmetric
 // fluxes f_S(u_p, u_q) = f_S(u_q, u_p) from its line neighbour through LDS.
 template <int N, int DIM>
 __device__ __forceinline__ int line_node(const int *pd, int d, int qd)
@@ -215,7 +215,9 @@ template <typename real, int EQ, int DIM, int N, int FLUX>
 struct LocalShape {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
     static constexpr int n1 = N + 1;
-    static constexpr bool SYM = (EQ == EQ_EULER) && (N >= 2);
+    // the conservative two-point fluxes are symmetric for both systems (the
+    // MHD non-conservative term is formed separately)
+    static constexpr bool SYM = N >= 2;
     static constexpr int NPRIM = SYM ? (n1 - 1) / 2 : 0;           // rotations whose mirror comes from LDS
     static constexpr int KSELF = (SYM && n1 % 2 == 0) ? n1 / 2 : 0;  // self-mirrored rotation, evaluated directly
     static constexpr int NX = SYM ? DIM * NPRIM * Phys::M : 0;
@@ -817,6 +819,11 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
 #pragma unroll
             for (int v = 0; v < M; ++v) u[v] += side ? -coef * jump[v] : coef * jump[v];
         }
+    }
+    // the pipelined step has every node in registers and writes whole
+    // elements (whole cache lines: no read of the lines it only partly
+    // writes); otherwise only the face nodes are written
+    if (face_lane || (tail && valid)) {
 #pragma unroll
         for (int v = 0; v < M; ++v) uo[((long)v * E + e) * NP + node] = u[v];
     }
