@@ -41,34 +41,60 @@ template <typename real> struct LnMeanSwitch;
 template <> struct LnMeanSwitch<double> { static constexpr double value = 1e-4; };
 template <> struct LnMeanSwitch<float> { static constexpr float value = 1e-2f; };
 
-// Logarithmic mean (x - y)/(ln x - ln y) from precomputed logarithms, and its
-// reciprocal.  With f = (x - y)/(x + y), u = f^2: ln(x/y) = 2 artanh f =
+// Reciprocal by Newton's iteration r <- r (2 - x r) from the hardware
+// estimate: one step (est1) leaves about 1 ulp in FP64, two steps converge.
+__device__ __forceinline__ double rcp_est1(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_est1(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float rcp_nr(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// Logarithmic mean (x - y)/(ln x - ln y) from precomputed logarithms.
+// With f = (x - y)/(x + y), u = f^2: ln(x/y) = 2 artanh f =
 // 2 f (1 + u/3 + u^2/5 + u^3/7 + ...), so near x = y the mean is
 // (x + y) / (2 (1 + u/3 + u^2/5 + u^3/7)).  Both branches are evaluated and
 // selected so that a wavefront never diverges here.
+//
+// Numerator and denominator of the logarithmic mean without a division: u
+// only selects the branch and feeds the series (where an error e in u moves
+// the mean by about e u / 3), so it takes the one-step reciprocal.
 template <typename real>
-__device__ __forceinline__ void lnmean_parts(real x, real y, real lx, real ly, real &num, real &den)
+__device__ __forceinline__ void lnmean_parts_fast(real x, real y, real lx, real ly, real &num, real &den)
 {
     const real s = x + y, d = x - y;
-    const real u = (d * d) / (s * s);
+    const real u = (d * d) * rcp_est1(s * s);
     const bool series = u < LnMeanSwitch<real>::value;
     const real poly = real(2) * (real(1) + u * (real(1) / real(3) + u * (real(1) / real(5) + u * (real(1) / real(7)))));
     num = series ? s : (y - x);
     den = series ? poly : (ly - lx);
 }
+
+// The two means an EC flux needs, ln-mean(x1, y1) and 1/ln-mean(x2, y2), with
+// one reciprocal: r = 1/(d1 n2), m1 = n1 n2 r = n1/d1, im2 = d2 d1 r = d2/n2.
+// Swapping the states flips the sign of n and d in the log branch and of
+// nothing in the series branch, so both results are symmetric bit for bit.
 template <typename real>
-__device__ __forceinline__ real lnmean(real x, real y, real lx, real ly)
+__device__ __forceinline__ void lnmean_pair(real x1, real y1, real lx1, real ly1, real x2, real y2, real lx2,
+                                            real ly2, real &m1, real &im2)
 {
-    real n, d;
-    lnmean_parts(x, y, lx, ly, n, d);
-    return n / d;
-}
-template <typename real>
-__device__ __forceinline__ real inv_lnmean(real x, real y, real lx, real ly)
-{
-    real n, d;
-    lnmean_parts(x, y, lx, ly, n, d);
-    return d / n;
+    real n1, d1, n2, d2;
+    lnmean_parts_fast(x1, y1, lx1, ly1, n1, d1);
+    lnmean_parts_fast(x2, y2, lx2, ly2, n2, d2);
+    const real r = rcp_nr(d1 * n2);
+    m1 = (n1 * n2) * r;
+    im2 = (d2 * d1) * r;
 }
 
 // ---------------------------------------------------------------- Euler
@@ -187,8 +213,9 @@ struct EulerP {
             for (int k = 0; k < DIM; ++k) f[1 + k] = (k == d ? m * vd + p : m * (a[1 + k] + b[1 + k]));
             f[DIM + 1] = (rho * e + p) * vd;
         } else {
-            const real rho_ln = lnmean(a[0], b[0], a[DIM + 2], b[DIM + 2]);
-            const real ibeta_ln = inv_lnmean(a[DIM + 3], b[DIM + 3], a[DIM + 4], b[DIM + 4]);
+            real rho_ln, ibeta_ln;
+            lnmean_pair(a[0], b[0], a[DIM + 2], b[DIM + 2], a[DIM + 3], b[DIM + 3], a[DIM + 4], b[DIM + 4], rho_ln,
+                        ibeta_ln);
             const real vd = real(0.5) * (a[1 + d] + b[1 + d]);
             real vv = real(0);
 #pragma unroll
@@ -300,8 +327,8 @@ struct MhdP {
             return;
         }
         const real h = real(0.5);
-        const real rho_ln = lnmean(a[0], b[0], a[9], b[9]);
-        const real ibeta_ln = inv_lnmean(a[10], b[10], a[11], b[11]);
+        real rho_ln, ibeta_ln;
+        lnmean_pair(a[0], b[0], a[9], b[9], a[10], b[10], a[11], b[11], rho_ln, ibeta_ln);
         const real rho_a = h * (a[0] + b[0]), beta_a = h * (a[10] + b[10]), psi_a = h * (a[8] + b[8]);
         real va[3], Ba[3];
 #pragma unroll
@@ -310,7 +337,7 @@ struct MhdP {
         f[0] = f0;
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            f[1 + k] = f0 * va[k] - Ba[d] * Ba[k] + (k == d ? rho_a / (real(2) * beta_a) + h * h * (a[13] + b[13]) : real(0));
+            f[1 + k] = f0 * va[k] - Ba[d] * Ba[k] + (k == d ? rho_a * rcp_nr(real(2) * beta_a) + h * h * (a[13] + b[13]) : real(0));
 #pragma unroll
         for (int k = 0; k < 3; ++k) f[5 + k] = (k == d) ? c.ch * psi_a : va[d] * Ba[k] - va[k] * Ba[d];
         f[8] = c.ch * Ba[d];
