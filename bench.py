@@ -36,9 +36,12 @@ PEAK_FP32_TFLOPS = 157.3
 # calibration) and FP64 FLOPs = SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes; valid only
 # for the kernel sources whose digest is recorded with them.
 MEASURED_TRAFFIC = {
-    ("khi256", "fp64"): {"sources_sha256": "4a4b2fabe095b0b73527d8e53c0387ec6af2482331d1782856c733d95650e4ad",
-                         "bytes": (2.0 * 24197.2 + 1.0 * 66048.0) * 1024,
+    ("khi256", "fp64"): {"sources_sha256": "e7aff613adefc77f916a476c018089c367fcba7df22a04649885522f1649fd06",
+                         "bytes": (2.0 * 24197.4 + 1.0 * 66048.0) * 1024,
                          "fp64_flops": 17612800.0 * 64},
+    ("khi256_ranocha", "fp64"): {"sources_sha256": "e7aff613adefc77f916a476c018089c367fcba7df22a04649885522f1649fd06",
+                                 "bytes": (2.0 * 24287.7 + 1.0 * 66048.0) * 1024,
+                                 "fp64_flops": 45203456.0 * 64},
 }
 KERNEL_SOURCES = ("paper_2604_02125_amd/csrc/crk_kernels.hpp", "paper_2604_02125_amd/csrc/crk_physics.hpp")
 
@@ -189,10 +192,16 @@ def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, thread
     xi, _, _ = crk.reference_element(3)
     u0 = inputs.kelvin_helmholtz(n, n, xi)
     pipe = Pipelined(s, u0)
-    el, _ = timed(pipe, steps, warmup)
+    el, k2_ms = timed(pipe, steps, warmup, events=True)
     check_admissible(s, pipe.state, f"khi{n}")
     ndof = s.nelem * s.shape[2]
-    out = {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps}
+    out = {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
+           "k_local_ms": k2_ms}
+    key = (f"khi{n}" + ("_ranocha" if flux == crk.VOL_RANOCHA else ""), "fp64" if precision == crk.FP64 else "fp32")
+    rec = MEASURED_TRAFFIC.get(key)
+    if rec and rec["sources_sha256"] == sources_digest() and flux is not None:
+        out["k_local_fp64_tflops"] = rec["fp64_flops"] / (k2_ms * 1e-3) / 1e12
+        out["k_local_fp64_frac"] = out["k_local_fp64_tflops"] / PEAK_FP64_TFLOPS
     if err_steps:
         p = orc.Problem(dim=2, nx=n, ny=n, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3,
                         vol_flux=orc.VOL_KG if flux is None else flux, limiter=orc.LIM_BLEND_MODAL, nthreads=threads)
