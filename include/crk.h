@@ -188,6 +188,14 @@ crk_status crk_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev
 crk_status crk_prepare(crk_solver *s, const void *u, double *dt_dev, crk_stream stream);
 crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, int phases, crk_stream stream);
 
+/* nsteps pipelined steps (as nsteps calls of crk_advance with both phases,
+ * alternating u0 -> u1 -> u0 ...): after an even count the state is in u0,
+ * after an odd count in u1; dt_dev as for crk_advance.  A one-dimensional
+ * Euler mesh of at most 256 nodes (without a bound network) runs all steps
+ * in one launch of one workgroup; other meshes issue the steps one by one.
+ * Needs crk_prepare on u0 first and the workspace. */
+crk_status crk_run(crk_solver *s, void *u0, void *u1, double *dt_dev, int nsteps, crk_stream stream);
+
 /* FP64 diagnostics of u into out_dev (device, nvar + 5 doubles):
  * totals sum_e sum_p w_p u_p |Omega_e| (nvar), total entropy
  * sum w_p S(u_p) |Omega_e| with S = -rho (ln p - gamma ln rho)/(gamma-1),

@@ -73,6 +73,7 @@ def lib():
             "crk_indicator": (st, [_vp, _vp, _vp, _vp, _vp]),
             "crk_local_stages": (st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "crk_interface_update": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
+            "crk_run": (st, [_vp, _vp, _vp, _vp, C.c_int, _vp]),
             "crk_step": (st, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp]),
             "crk_diagnostics": (st, [_vp, _vp, _vp, _vp]),
             "crk_prepare": (st, [_vp, _vp, _vp, _vp]),
@@ -221,6 +222,14 @@ class Solver:
         self._check_state(u_out)
         _check(lib().crk_advance(self._h, _ptr(u_in), _ptr(u_out), _ptr(dt), int(phases), _stream(stream)),
                "crk_advance")
+
+    def run(self, u0, u1, dt, nsteps, stream=None):
+        """nsteps pipelined steps alternating u0 -> u1 -> u0 ...; returns the
+        tensor that holds the final state."""
+        self._check_state(u0)
+        self._check_state(u1)
+        _check(lib().crk_run(self._h, _ptr(u0), _ptr(u1), _ptr(dt), int(nsteps), _stream(stream)), "crk_run")
+        return u1 if nsteps % 2 else u0
 
     def diagnostics(self, u, stream=None):
         import torch

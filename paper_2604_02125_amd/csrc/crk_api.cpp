@@ -531,6 +531,36 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
     return CRK_OK;
 }
 
+crk_status crk_run(crk_solver *s, void *u0, void *u1, double *dt_dev, int nsteps, crk_stream stream)
+{
+    crk_status st = need_ws(s);
+    if (st) return st;
+    if (!u0 || !u1 || !dt_dev) return fail(CRK_ERR_ARG, "null pointer");
+    if (u0 == u1) return fail(CRK_ERR_ARG, "u0 and u1 must not alias");
+    if (nsteps < 0) return fail(CRK_ERR_ARG, "negative step count");
+    if (!is_aligned(u0) || !is_aligned(u1)) return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
+    if (!s->prepared) return fail(CRK_ERR_STATE, "crk_prepare must run before crk_run");
+    if (nsteps == 0) return CRK_OK;
+    const bool lim = s->limiter == CRK_LIM_BLEND;
+    if (s->mesh.dim == 1 && (long)s->t.nelem * s->t.nnode <= RUN_BLOCK && !s->mlp) {
+        StepPtrs p{};
+        p.u_in = u0; p.u_out = u1; p.dt = dt_dev; p.traces = s->ws + s->off_traces;
+        p.alpha_raw = lim ? (double *)(s->ws + s->off_araw) : nullptr;
+        p.alpha_s = (double *)(s->ws + s->off_alpha);
+        p.alpha_raw_out = lim ? (double *)(s->ws + s->off_araw) : nullptr;
+        p.partials = (double *)(s->ws + s->off_partials);
+        hipError_t e = dispatch(s, [&](auto fam) {
+            return decltype(fam)::run(s->t, s->flux, p, dt_dev, nsteps, (hipStream_t)stream); });
+        if (e == hipSuccess) return CRK_OK;
+        if (e != hipErrorNotSupported) return hip_fail(e, "crk_run");
+    }
+    for (int k = 0; k < nsteps; ++k) {
+        st = crk_advance(s, k % 2 ? u1 : u0, k % 2 ? u0 : u1, dt_dev, CRK_PHASE_LOCAL | CRK_PHASE_INTERFACE, stream);
+        if (st) return st;
+    }
+    return CRK_OK;
+}
+
 crk_status crk_diagnostics(crk_solver *s, const void *u, double *out_dev, crk_stream stream)
 {
     crk_status st = need_ws(s);

@@ -35,22 +35,19 @@ struct BatchTile {
     int e0;
 };
 
-template <typename real, int FLUX>
-constexpr int batch_slots()
+// Local phase over the tiles [t0, t1) of one degree (the work list holds the
+// degree-3 tiles first): one kernel per degree, so that each is compiled and
+// scheduled with its own register budget (the six-stage degree-4 path needs
+// far more registers than the four-stage degree-3 one).
+template <typename real, int FLUX, int BLK, int NDEG>
+__global__ void __launch_bounds__(BLK) k_batch_local(const BatchProblem *probs, const BatchTile *tiles, int t0, int t1,
+                                                     int dir)
 {
-    constexpr int a = LocalShape<real, EQ_EULER, 2, 3, FLUX>::slots;
-    constexpr int b = LocalShape<real, EQ_EULER, 2, 4, FLUX>::slots;
-    return a > b ? a : b;
-}
-
-template <typename real, int FLUX, int BLK>
-__global__ void __launch_bounds__(BLK) k_batch_local(const BatchProblem *probs, const BatchTile *tiles, int ntiles, int dir)
-{
-    __shared__ real smem[batch_slots<real, FLUX>() * BLK];
-    for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
+    __shared__ real smem[LocalShape<real, EQ_EULER, 2, NDEG, FLUX>::slots * BLK];
+    for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
         const BatchTile tl = tiles[it];
         const BatchProblem &bp = probs[tl.prob];
-        if (bp.t.N == 3) local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK, 1>(bp.t, bp.p[dir], tl.e0, smem);
+        if constexpr (NDEG == 3) local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK, 1>(bp.t, bp.p[dir], tl.e0, smem);
         else local_tile<real, EQ_EULER, 2, 4, FLUX, 6, BLK>(bp.t, bp.p[dir], tl.e0, smem);
         __syncthreads();
     }
@@ -146,7 +143,8 @@ struct crk_batch {
     int nprob, prec, flux, block, grid;
     std::vector<crk_mesh_desc> mesh;
     std::vector<BatchProblem> probs;     // host copy of the descriptors
-    std::vector<BatchTile> tiles;
+    std::vector<BatchTile> tiles;        // degree-3 problems' tiles first, then degree 4
+    int ntiles3;                         // number of degree-3 tiles
     std::vector<long> state_off;         // values
     size_t state_bytes;
     std::vector<size_t> trace_off;       // bytes inside the workspace trace area
@@ -168,8 +166,15 @@ hipError_t launch_phase(const crk_batch *b, int kind, int dir, hipStream_t s)
     double *parts = (double *)(b->ws + b->off_parts);
     const int nt = (int)b->tiles.size();
     const int g = b->grid > 0 && b->grid < nt ? b->grid : nt;
-    if (kind == 0) hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir);
-    else if (kind == 1) hipLaunchKernelGGL((k_batch_interface<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir);
+    if (kind == 0) {
+        const int n3 = b->ntiles3, n4 = nt - n3;
+        if (n3 > 0)
+            hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 3>), dim3(b->grid > 0 && b->grid < n3 ? b->grid : n3),
+                               dim3(BLK), 0, s, pr, tl, 0, n3, dir);
+        if (n4 > 0)
+            hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 4>), dim3(b->grid > 0 && b->grid < n4 ? b->grid : n4),
+                               dim3(BLK), 0, s, pr, tl, n3, nt, dir);
+    } else if (kind == 1) hipLaunchKernelGGL((k_batch_interface<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir);
     else hipLaunchKernelGGL((k_batch_speed<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir, parts);
     if (kind != 0) hipLaunchKernelGGL(k_batch_dt, dim3(b->nprob), dim3(256), 0, s, pr, (const double *)parts, b->dt);
     return hipGetLastError();
@@ -260,10 +265,19 @@ crk_status crk_batch_create(const crk_mesh_desc *meshes, int nprob, const crk_sc
         b->trace_off[i] = toff;
         // four faces; per face node M flux-share values and the wave speed
         toff = align256(toff + (size_t)2 * 2 * (t.M + 1) * t.nelem * t.nface * elem);
-        const int epb = block / t.nnode;
-        b->probs[i].tile0 = (int)b->tiles.size();
-        for (int e0 = 0; e0 < t.nelem; e0 += epb) b->tiles.push_back(BatchTile{i, e0});
-        b->probs[i].ntiles = (int)b->tiles.size() - b->probs[i].tile0;
+    }
+    // work list: the tiles of the degree-3 problems, then those of degree 4;
+    // the tiles of one problem stay contiguous
+    for (int deg = 3; deg <= 4; ++deg) {
+        if (deg == 4) b->ntiles3 = (int)b->tiles.size();
+        for (int i = 0; i < nprob; ++i) {
+            const Tables &t = b->probs[i].t;
+            if (t.N != deg) continue;
+            const int epb = block / t.nnode;
+            b->probs[i].tile0 = (int)b->tiles.size();
+            for (int e0 = 0; e0 < t.nelem; e0 += epb) b->tiles.push_back(BatchTile{i, e0});
+            b->probs[i].ntiles = (int)b->tiles.size() - b->probs[i].tile0;
+        }
     }
     b->state_off[nprob] = off;
     b->trace_off[nprob] = toff;

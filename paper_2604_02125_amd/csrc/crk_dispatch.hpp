@@ -12,6 +12,9 @@ struct Family {
     static hipError_t interface(const Tables &t, int flux, const StepPtrs &p, hipStream_t s);
     // wave speeds of the face nodes of p.u_in into the face data p.traces
     static hipError_t face_speed(const Tables &t, int flux, const StepPtrs &p, hipStream_t s);
+    // nsteps pipelined steps of a one-dimensional mesh of at most RUN_BLOCK
+    // nodes in one workgroup (hipErrorNotSupported otherwise)
+    static hipError_t run(const Tables &t, int flux, const StepPtrs &p, double *dt, int nsteps, hipStream_t s);
     static hipError_t indicator(const Tables &t, const void *u, double *araw, double *alpha, float *features, hipStream_t s);
     static hipError_t dt(const Tables &t, const void *u, double *partials, double *dt, hipStream_t s);
     static hipError_t diag(const Tables &t, const void *u, double *partials, double *out, hipStream_t s);

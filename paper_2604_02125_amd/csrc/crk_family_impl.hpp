@@ -43,6 +43,31 @@ hipError_t Family<real, EQ, DIM>::face_speed(const Tables &t, int flux, const St
 }
 
 template <typename real, int EQ, int DIM>
+hipError_t Family<real, EQ, DIM>::run(const Tables &t, int flux, const StepPtrs &p, double *dt, int nsteps,
+                                      hipStream_t s)
+{
+    if constexpr (DIM != 1 || EQ != EQ_EULER) {
+        return hipErrorNotSupported;
+    } else {
+#define CRK_RUN_FLUX(NN)                                                                             \
+        switch (flux) {                                                                              \
+        case VOL_CENTRAL: return launch_run<real, EQ, DIM, NN, VOL_CENTRAL>(t, p, dt, nsteps, s);   \
+        case VOL_KG: return launch_run<real, EQ, DIM, NN, VOL_KG>(t, p, dt, nsteps, s);             \
+        case VOL_RANOCHA: return launch_run<real, EQ, DIM, NN, VOL_RANOCHA>(t, p, dt, nsteps, s);   \
+        default: return hipErrorInvalidValue;                                                        \
+        }
+        switch (t.N) {
+        case 1: CRK_RUN_FLUX(1)
+        case 2: CRK_RUN_FLUX(2)
+        case 3: CRK_RUN_FLUX(3)
+        case 4: CRK_RUN_FLUX(4)
+        default: return hipErrorInvalidValue;
+        }
+#undef CRK_RUN_FLUX
+    }
+}
+
+template <typename real, int EQ, int DIM>
 hipError_t Family<real, EQ, DIM>::indicator(const Tables &t, const void *u, double *araw, double *alpha, float *features,
                                             hipStream_t s)
 {

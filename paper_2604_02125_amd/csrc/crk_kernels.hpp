@@ -867,6 +867,58 @@ __global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 
     interface_tile<real, EQ, DIM, N, FLUX, TB>(t, a, (long)blockIdx.x * (TB / NP), blockIdx.x, dsmem);
 }
 
+// dt = cfl / ((N+1) m) from the global wave-speed maximum m (MHD: m = c_h and
+// every lambda_d equals it)
+__device__ __forceinline__ void finish_dt(const Tables &t, double m, int is_mhd, double *dt)
+{
+    if (is_mhd) {
+        // every lambda_d = max(|v_d| + c_f, c_h) equals c_h = the global max
+        double sdx = 0.0;
+        for (int d = 0; d < t.dim; ++d) sdx += t.invdx[d];
+        dt[0] = t.cfl / ((t.N + 1) * m * sdx);
+        dt[1] = m;
+    } else {
+        dt[0] = t.cfl / ((t.N + 1) * m);
+        dt[1] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- small meshes: every step in one workgroup
+// A mesh of up to RUN_BLOCK nodes fits one workgroup: the local phase, the
+// interface phase and the dt reduction of each pipelined step run back to
+// back inside one launch, separated by workgroup barriers.  The phases
+// exchange data through global memory written and read by the waves of one
+// CU, which the barriers' workgroup-scope ordering makes visible; dt lives in
+// LDS between the steps.  Same device code and arithmetic as the separate
+// launches.
+constexpr int RUN_BLOCK = 256;   // one wavefront per SIMD: no register cap
+template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB>
+__global__ void __launch_bounds__(RUN_BLOCK) k_run(const Tables t, const StepPtrs a0, double *dt_io, int nsteps)
+{
+    constexpr size_t LB = (size_t)LocalShape<real, EQ, DIM, N, FLUX>::slots * RUN_BLOCK * sizeof(real);
+    constexpr size_t DB = (size_t)5 * RUN_BLOCK * sizeof(double);
+    __shared__ double pool[(LB > DB ? LB : DB) / sizeof(double)];   // local phase, then interface phase
+    __shared__ double dtl[2];
+    const int tid = threadIdx.x;
+    StepPtrs ae = a0, ao = a0;         // even and odd steps
+    ao.u_in = a0.u_out;
+    ao.u_out = const_cast<void *>(a0.u_in);
+    ae.dt = ao.dt = dtl;
+    ae.dt_out = ao.dt_out = dtl;       // (non-null: the interface phase runs its tail)
+    if (tid == 0) { dtl[0] = dt_io[0]; dtl[1] = dt_io[1]; }
+    __syncthreads();
+    for (int k = 0; k < nsteps; ++k) {
+        const StepPtrs &p = (k & 1) ? ao : ae;
+        local_tile<real, EQ, DIM, N, FLUX, S, RUN_BLOCK, TAB>(t, p, 0, (real *)pool);
+        __syncthreads();
+        interface_tile<real, EQ, DIM, N, FLUX, RUN_BLOCK>(t, p, 0, 0, pool);
+        __syncthreads();
+        if (tid == 0) finish_dt(t, p.partials[0], EQ == EQ_MHD ? 1 : 0, dtl);
+        __syncthreads();
+    }
+    if (tid == 0) { dt_io[0] = dtl[0]; dt_io[1] = dtl[1]; }
+}
+
 // ---------------------------------------------------------------- K1: time step
 // Per node sum_d lambda_d/dx_d (Euler) or max_d (|v_d| + c_f) (MHD); block
 // maxima into partials, then one block finishes.  Deterministic, no atomics.
@@ -929,16 +981,7 @@ static __global__ void __launch_bounds__(FINAL_BLOCK) k_dt_final(const Tables t,
     if (tid == 0) {
         double m = red[0];
         for (int w = 1; w < FINAL_BLOCK / 64; ++w) m = fmax(m, red[w]);
-        if (is_mhd) {
-            // every lambda_d = max(|v_d| + c_f, c_h) equals c_h = the global max
-            double sdx = 0.0;
-            for (int d = 0; d < t.dim; ++d) sdx += t.invdx[d];
-            dt[0] = t.cfl / ((t.N + 1) * m * sdx);
-            dt[1] = m;
-        } else {
-            dt[0] = t.cfl / ((t.N + 1) * m);
-            dt[1] = 0.0;
-        }
+        finish_dt(t, m, is_mhd, dt);
     }
 }
 
@@ -1097,6 +1140,25 @@ hipError_t launch_interface(const Tables &t, const StepPtrs &p, hipStream_t s)
     if (p.dt_out != nullptr)
         hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(FINAL_BLOCK), 0, s, t, (const double *)p.partials, grid,
                            EQ == EQ_MHD ? 1 : 0, p.dt_out);
+    return hipGetLastError();
+}
+
+template <typename real, int EQ, int DIM, int N, int FLUX>
+hipError_t launch_run(const Tables &t, const StepPtrs &p, double *dt, int nsteps, hipStream_t s)
+{
+    constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
+    if ((long)t.nelem * NP > RUN_BLOCK) return hipErrorInvalidValue;
+#define CRK_RUN(SS, TT) hipLaunchKernelGGL((k_run<real, EQ, DIM, N, FLUX, SS, TT>), dim3(1), dim3(RUN_BLOCK), 0, s, t, p, dt, nsteps)
+    switch (t.stages) {
+    case 1: CRK_RUN(1, 0); break;
+    case 2: CRK_RUN(2, 0); break;
+    case 3: CRK_RUN(3, 0); break;
+    case 4: if (t.tableau == 1) CRK_RUN(4, 1); else CRK_RUN(4, 0); break;
+    case 5: CRK_RUN(5, 0); break;
+    case 6: CRK_RUN(6, 0); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef CRK_RUN
     return hipGetLastError();
 }
 

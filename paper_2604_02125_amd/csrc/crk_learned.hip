@@ -232,19 +232,18 @@ __global__ void __launch_bounds__(256) k_to_bf16(long count, const float *x, uin
 typedef short mx_s4 __attribute__((ext_vector_type(4)));
 typedef float mx_f4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ short bf_bits(float f) { return (short)f2bf(f); }
-
+// x = hi + mid + lo in BF16 (round to nearest even: the hardware conversion)
 __device__ __forceinline__ void split3(const float *x, mx_s4 &h, mx_s4 &m, mx_s4 &l)
 {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const uint16_t bh = f2bf(x[i]);
-        const float r1 = x[i] - bf2f(bh);
-        const uint16_t bm = f2bf(r1);
-        const float r2 = r1 - bf2f(bm);
-        h[i] = (short)bh;
-        m[i] = (short)bm;
-        l[i] = bf_bits(r2);
+        const __bf16 bh = (__bf16)x[i];
+        const float r1 = x[i] - (float)bh;
+        const __bf16 bm = (__bf16)r1;
+        const float r2 = r1 - (float)bm;
+        h[i] = __builtin_bit_cast(short, bh);
+        m[i] = __builtin_bit_cast(short, bm);
+        l[i] = __builtin_bit_cast(short, (__bf16)r2);
     }
 }
 

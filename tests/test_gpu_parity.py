@@ -381,3 +381,42 @@ def test_pipelined_advance(orc, case):
         s.advance(b3[n % 2], b3[(n + 1) % 2], d3, phases=crk.PHASE_INTERFACE)
     torch.cuda.synchronize()
     assert torch.equal(b3[nsteps % 2], buf[nsteps % 2])
+
+
+@pytest.mark.parametrize("case", ["wave1d_fused", "wave1d_blend_fused", "khi2d_loop", "odd_steps"])
+def test_run_many_steps(orc, case):
+    """crk_run: all steps of a small 1D mesh in one launch (and the step loop
+    for other meshes) give bit for bit the states and dt of crk_advance
+    called step by step; the 1D density wave matches the oracle after 200
+    steps."""
+    nsteps = {"wave1d_fused": 200, "wave1d_blend_fused": 25, "khi2d_loop": 4, "odd_steps": 7}[case]
+    if case == "khi2d_loop":
+        p, s = _pair(orc, dim=2, nx=12, ny=10, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=1,
+                     limiter=orc.LIM_BLEND_MODAL)
+    elif case == "wave1d_blend_fused":
+        p, s = _pair(orc, dim=1, nx=50, N=4, vol_flux=1, limiter=orc.LIM_BLEND_MODAL)
+    else:
+        p, s = _pair(orc, dim=1, nx=64, N=3, vol_flux=2)
+    xi, _ = orc.gll(p.N)
+    u = inputs.density_wave_1d(p.nx, xi) if p.dim == 1 else _state(orc, p, seed=61)
+    if case == "wave1d_blend_fused":
+        u = inputs.perturb(u, 5, 3e-2)
+    ug = torch.tensor(u, device="cuda")
+    a = [ug.clone(), s.new_state()]
+    da = s.new_dt()
+    s.prepare(a[0], da)
+    for n in range(nsteps):
+        s.advance(a[n % 2], a[(n + 1) % 2], da)
+    b = [ug.clone(), s.new_state()]
+    db = s.new_dt()
+    s.prepare(b[0], db)
+    out = s.run(b[0], b[1], db, nsteps)
+    torch.cuda.synchronize()
+    assert out is b[nsteps % 2]
+    assert torch.equal(out, a[nsteps % 2])
+    assert torch.equal(db, da)
+    if case == "wave1d_fused":
+        ref = u.copy()
+        for _ in range(nsteps):
+            ref, _ = orc.crk_step(p, ref, orc.compute_dt(p, ref))
+        assert _rel(out.cpu().numpy(), ref) <= 1e-11     # 200 steps of per-step round-off
