@@ -38,18 +38,31 @@ struct BatchTile {
 // Local phase over the tiles [t0, t1) of one degree (the work list holds the
 // degree-3 tiles first): one kernel per degree, so that each is compiled and
 // scheduled with its own register budget (the six-stage degree-4 path needs
-// far more registers than the four-stage degree-3 one).
-template <typename real, int FLUX, int BLK, int NDEG>
+// far more registers than the four-stage degree-3 one).  PERSIST: a fixed
+// grid of workgroups walks the tiles; else one workgroup per tile.  In the
+// persistent loop the lane index passes through an empty asm statement so
+// that the compiler recomputes the lane's per-node constants in every
+// iteration instead of keeping them live across the whole loop.
+template <typename real, int FLUX, int BLK, int NDEG, bool PERSIST>
 __global__ void __launch_bounds__(BLK) k_batch_local(const BatchProblem *probs, const BatchTile *tiles, int t0, int t1,
                                                      int dir)
 {
     __shared__ real smem[LocalShape<real, EQ_EULER, 2, NDEG, FLUX>::slots * BLK];
-    for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
+    auto tile = [&](int it, int lane) {
         const BatchTile tl = tiles[it];
         const BatchProblem &bp = probs[tl.prob];
-        if constexpr (NDEG == 3) local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK, 1>(bp.t, bp.p[dir], tl.e0, smem);
-        else local_tile<real, EQ_EULER, 2, 4, FLUX, 6, BLK>(bp.t, bp.p[dir], tl.e0, smem);
-        __syncthreads();
+        if constexpr (NDEG == 3) local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK, 1>(bp.t, bp.p[dir], tl.e0, smem, lane);
+        else local_tile<real, EQ_EULER, 2, 4, FLUX, 6, BLK>(bp.t, bp.p[dir], tl.e0, smem, lane);
+    };
+    if constexpr (PERSIST) {
+        for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
+            int lane = threadIdx.x;
+            asm volatile("" : "+v"(lane));
+            tile(it, lane);
+            __syncthreads();
+        }
+    } else {
+        tile(t0 + blockIdx.x, threadIdx.x);      // the grid is exactly the tile count
     }
 }
 
@@ -168,12 +181,21 @@ hipError_t launch_phase(const crk_batch *b, int kind, int dir, hipStream_t s)
     const int g = b->grid > 0 && b->grid < nt ? b->grid : nt;
     if (kind == 0) {
         const int n3 = b->ntiles3, n4 = nt - n3;
-        if (n3 > 0)
-            hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 3>), dim3(b->grid > 0 && b->grid < n3 ? b->grid : n3),
-                               dim3(BLK), 0, s, pr, tl, 0, n3, dir);
-        if (n4 > 0)
-            hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 4>), dim3(b->grid > 0 && b->grid < n4 ? b->grid : n4),
-                               dim3(BLK), 0, s, pr, tl, n3, nt, dir);
+        if (b->grid > 0) {
+            if (n3 > 0)
+                hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 3, true>), dim3(b->grid < n3 ? b->grid : n3),
+                                   dim3(BLK), 0, s, pr, tl, 0, n3, dir);
+            if (n4 > 0)
+                hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 4, true>), dim3(b->grid < n4 ? b->grid : n4),
+                                   dim3(BLK), 0, s, pr, tl, n3, nt, dir);
+        } else {
+            if (n3 > 0)
+                hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 3, false>), dim3(n3), dim3(BLK), 0, s, pr, tl, 0,
+                                   n3, dir);
+            if (n4 > 0)
+                hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 4, false>), dim3(n4), dim3(BLK), 0, s, pr, tl, n3,
+                                   nt, dir);
+        }
     } else if (kind == 1) hipLaunchKernelGGL((k_batch_interface<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir);
     else hipLaunchKernelGGL((k_batch_speed<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir, parts);
     if (kind != 0) hipLaunchKernelGGL(k_batch_dt, dim3(b->nprob), dim3(256), 0, s, pr, (const double *)parts, b->dt);

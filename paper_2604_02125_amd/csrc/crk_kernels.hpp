@@ -230,7 +230,7 @@ struct LocalShape {
 // One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
 // smem holds LocalShape::slots * BLK values.
 template <typename real, int EQ, int DIM, int N, int FLUX, int S, int BLK, int TAB = 0>
-__device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, long e0, real *smem)
+__device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, long e0, real *smem, int lane = -1)
 {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
     using Shape = LocalShape<real, EQ, DIM, N, FLUX>;
@@ -248,7 +248,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     real *llds = alds + 2 * BLK;          // [DIM][BLK]
     constexpr int NA = 2 * DIM + 1;
 
-    const int tid = threadIdx.x;
+    const int tid = lane >= 0 ? lane : (int)threadIdx.x;   // (lane: see the batched local phase)
     int le = tid / NP;
     const int node = tid - le * NP;
     const long e = e0 + le;
