@@ -182,7 +182,12 @@ crk_status crk_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev
  * arithmetic as crk_step; only the CFL reduction and the indicator move
  * into the interface phase.  `phases` selects CRK_PHASE_LOCAL and/or
  * CRK_PHASE_INTERFACE (both = one full step; the phases of one step must
- * be issued in this order on one stream).  Needs the workspace. */
+ * be issued in this order on one stream).  Needs the workspace.  The
+ * interface phase merges per-workgroup wave-speed maxima into a small slot
+ * array of the workspace that crk_prepare sets to zero and each interface
+ * phase leaves at zero; two pipelined sequences must therefore not run on
+ * one solver at once, and a failed interface phase requires crk_prepare
+ * again (CRK_ERR_STATE). */
 #define CRK_PHASE_LOCAL 1
 #define CRK_PHASE_INTERFACE 2
 crk_status crk_prepare(crk_solver *s, const void *u, double *dt_dev, crk_stream stream);

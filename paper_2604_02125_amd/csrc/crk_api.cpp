@@ -124,7 +124,7 @@ struct crk_solver {
     Tables t;
     size_t elem_bytes;
     size_t state_bytes, trace_bytes;
-    size_t off_partials, off_araw, off_alpha, off_features, off_traces, ws_bytes;
+    size_t off_partials, off_slots, off_araw, off_alpha, off_features, off_traces, ws_bytes;
     const uint16_t *mlp;          // learned indicator parameters (BF16, device) or nullptr
     const float *mlp_lo, *mlp_hi; // feature range the network was trained on
     char *ws;
@@ -242,12 +242,17 @@ crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables
         t.b[0] = 7.0 / 90; t.b[2] = 32.0 / 90; t.b[3] = 12.0 / 90; t.b[4] = 32.0 / 90; t.b[5] = 7.0 / 90;
     }
     {
-        // classical RK4 gets a kernel that keeps one pending stage increment
+        // classical RK4 gets a kernel that keeps one pending stage increment;
+        // a six-stage matrix with Butcher's zero pattern one that forms only
+        // the partial stage sums that pattern couples
         const double A4[4][4] = {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {0, 0.5, 0, 0}, {0, 0, 1, 0}};
         bool rk4 = t.stages == 4;
         for (int i = 0; rk4 && i < 4; ++i)
             for (int j = 0; j < 4; ++j) rk4 = rk4 && t.A[i][j] == A4[i][j];
-        t.tableau = rk4 ? 1 : 0;
+        bool b6 = t.stages == 6;
+        for (int k = 0; b6 && k < 6; ++k)
+            for (int i = 0; i < 6; ++i) b6 = b6 && (stage_coupled<2>(k, i) || t.A[k][i] == 0.0);
+        t.tableau = rk4 ? 1 : (b6 ? 2 : 0);
     }
     double xi[MAXN + 1], w[MAXN + 1], D[(MAXN + 1) * (MAXN + 1)];
     gll_nodes(t.N, xi, w);
@@ -296,6 +301,7 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     const long elem_blocks = (nelem + epb - 1) / epb;
     const long nparts = elem_blocks > RED_BLOCKS * 16 ? elem_blocks : RED_BLOCKS * 16;
     s->off_partials = off; off = align256(off + sizeof(double) * nparts);
+    s->off_slots = off; off = align256(off + sizeof(double) * DT_SLOTS);
     s->off_araw = off; off = align256(off + sizeof(double) * nelem);
     s->off_alpha = off; off = align256(off + sizeof(double) * nelem);
     s->off_features = off; off = align256(off + sizeof(float) * nelem * nnode);
@@ -488,6 +494,9 @@ crk_status crk_prepare(crk_solver *s, const void *u, double *dt_dev, crk_stream 
     StepPtrs p{};
     p.u_in = u; p.traces = s->ws + s->off_traces;
     hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::face_speed(s->t, s->flux, p, (hipStream_t)stream); });
+    // the wave-speed slots the interface phases merge into start at zero
+    // (a fill kernel, not a memset: safe inside a captured graph)
+    if (e == hipSuccess) e = launch_zero((double *)(s->ws + s->off_slots), DT_SLOTS, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "crk_prepare");
     s->prepared = true;
     return CRK_OK;
@@ -519,14 +528,17 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
         StepPtrs p{};
         p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = tr;
         p.alpha_raw_out = lim ? araw : nullptr;
-        p.partials = (double *)(s->ws + s->off_partials);
+        p.partials = (double *)(s->ws + s->off_slots);
         p.dt_out = dt_dev;
         p.features = (lim && s->mlp) ? (float *)(s->ws + s->off_features) : nullptr;
         e = dispatch(s, [&](auto fam) { return decltype(fam)::interface(s->t, s->flux, p, (hipStream_t)stream); });
         if (e == hipSuccess && p.features)
             e = launch_mlp_alpha(s->mlp, p.features, s->mlp_lo, s->mlp_hi, s->t.nelem, s->t.alpha_max,
                                  s->t.alpha_min, araw, (hipStream_t)stream);
-        if (e != hipSuccess) return hip_fail(e, "crk_advance (interface phase)");
+        if (e != hipSuccess) {
+            s->prepared = false;   // the slots may not be back at zero
+            return hip_fail(e, "crk_advance (interface phase)");
+        }
     }
     return CRK_OK;
 }

@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(BLK) k_batch_local(const BatchProblem *probs, 
         const BatchTile tl = tiles[it];
         const BatchProblem &bp = probs[tl.prob];
         if constexpr (NDEG == 3) local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK, 1>(bp.t, bp.p[dir], tl.e0, smem, lane);
-        else local_tile<real, EQ_EULER, 2, 4, FLUX, 6, BLK>(bp.t, bp.p[dir], tl.e0, smem, lane);
+        else local_tile<real, EQ_EULER, 2, 4, FLUX, 6, BLK, 2>(bp.t, bp.p[dir], tl.e0, smem, lane);
     };
     if constexpr (PERSIST) {
         for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {

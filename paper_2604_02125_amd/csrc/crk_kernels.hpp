@@ -34,7 +34,7 @@ struct Tables {
     double inv_nx;                    // 1/nx, for the element coordinates
     double gamma;
     int stages;
-    int tableau;                      // 1: classical RK4 (a_{i+1,i} only), 0: general
+    int tableau;                      // sparsity class of A: see stage_coupled()
     double A[MAXS][MAXS];
     double b[MAXS];
     double D[MAXN + 1][MAXN + 1];     // D_pq = l_q'(xi_p) on [0,1]
@@ -44,6 +44,29 @@ struct Tables {
     double cfl;
     double ind_threshold, ind_sharpness, alpha_min, alpha_max;
 };
+
+// Which entries a_ki (k > i) of the stage matrix a kernel may treat as
+// non-zero: TAB 0 any, TAB 1 only a_{i+1,i} (classical RK4), TAB 2 the
+// pattern of Butcher's six-stage fifth-order method (a_10; a_20, a_21;
+// a_31, a_32; a_40, a_43; a_5j).  The values always come from Tables::A; the
+// pattern only decides which partial stage sums Z_k = sum_j a_kj R^(j) are
+// formed, so that those still pending stay few (registers).
+template <int TAB>
+__host__ __device__ constexpr bool stage_coupled(int k, int i)
+{
+    if (k <= i) return false;
+    if (TAB == 1) return k == i + 1;
+    if (TAB == 2) {
+        switch (k) {
+        case 1: return i == 0;
+        case 2: return i <= 1;
+        case 3: return i == 1 || i == 2;
+        case 4: return i == 0 || i == 3;
+        default: return true;
+        }
+    }
+    return true;
+}
 
 struct StepPtrs {
     const void *u_in;
@@ -57,8 +80,8 @@ struct StepPtrs {
     const double *alpha_raw;  // local phase: raw indicator of u_in, or nullptr
     double *alpha_s;          // local phase: smoothed coefficients written for the interface phase
     double *alpha_raw_out;    // interface phase: raw indicator of u_out, or nullptr
-    double *partials;         // interface phase: per-workgroup wave-speed maxima
-    double *dt_out;           // interface phase: dt and c_h of u_out (finished by k_dt_final), or nullptr
+    double *partials;         // interface phase: wave-speed maxima (k_interface: DT_SLOTS slots, zero on entry)
+    double *dt_out;           // interface phase: dt and c_h of u_out (finished by k_dt_slots), or nullptr
     float *features;          // interface phase: learned-indicator features of u_out, or nullptr
 };
 
@@ -579,6 +602,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         } else {
 #pragma unroll
             for (int k = i + 1; k < S; ++k) {
+                if (!stage_coupled<TAB>(k, i)) continue;
                 const real aki = real(t.A[k][i]);
 #pragma unroll
                 for (int v = 0; v < M; ++v) Z[k][v] += aki * R[v];
@@ -716,9 +740,14 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
         features[e * NP + node] = (float)(1.0 + log10(fmax(e2 / tot, 1e-16)) / 16.0);
 }
 
-// Workgroup maximum of v (all lanes call) into partials[blockIdx.x]; a
-// one-workgroup kernel finishes the reduction after the grid has drained.
-template <int BLK>
+// Workgroup maximum of v (all lanes call) into *slot; a one-workgroup kernel
+// finishes the reduction after the grid has drained.  With ATOMIC the
+// maximum is merged into *slot (which must start at zero) by an integer
+// atomic maximum on the bit pattern: for non-negative doubles the integer
+// order is the numeric order, so the merged value is exact and does not
+// depend on the order of the merges.  A NaN maximum (every lane NaN) counts
+// as zero, as fmax would treat it.
+template <int BLK, bool ATOMIC = false>
 __device__ __forceinline__ void block_max_lanes(double v, double *red, double *slot)
 {
     // maximum over the wavefront by butterfly, then over the BLK/64 wavefronts
@@ -726,15 +755,31 @@ __device__ __forceinline__ void block_max_lanes(double v, double *red, double *s
     const int tid = threadIdx.x;
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
-    if ((tid & 63) == 0) red[tid >> 6] = v;
-    __syncthreads();
+    if constexpr (BLK > 64) {
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+    }
     if (tid == 0) {
-        double r = red[0];
+        double r = v;
+        if constexpr (BLK > 64) {
+            r = red[0];
 #pragma unroll
-        for (int w = 1; w < BLK / 64; ++w) r = fmax(r, red[w]);
-        *slot = r;
+            for (int w = 1; w < BLK / 64; ++w) r = fmax(r, red[w]);
+        }
+        if constexpr (ATOMIC) {
+            const double rr = r >= 0.0 ? r : 0.0;
+            atomicMax((unsigned long long *)slot, (unsigned long long)__double_as_longlong(rr));
+        } else {
+            *slot = r;
+        }
     }
 }
+
+// Slots of the pipelined step's wave-speed maximum: interface-phase
+// workgroup b merges its maximum into slot b mod DT_SLOTS; k_dt_slots reads
+// every slot once (one load per lane), puts it back to zero for the next
+// step and finishes dt.  Far fewer loads than one partial per workgroup.
+constexpr int DT_SLOTS = 1024;
 
 // ---------------------------------------------------------------- K3: interface + final update
 // One lane per node; the face-node lanes apply the interface corrections.
@@ -742,9 +787,10 @@ __device__ __forceinline__ void block_max_lanes(double v, double *red, double *s
 // started from.  In the pipelined step every lane then holds u^{n+1} of its
 // node and the workgroup computes the CFL maximum and the raw indicator.
 // One tile of BLK lanes (elements e0 .. e0 + BLK/(N+1)^DIM - 1).  In the
-// pipelined step the tile's wave-speed maximum goes to partials[slot]; dsmem
-// holds 5 * BLK doubles.
-template <typename real, int EQ, int DIM, int N, int FLUX, int BLK>
+// pipelined step the tile's wave-speed maximum goes to partials[slot] (with
+// SLOTS: is merged into partials[slot mod DT_SLOTS]); dsmem holds 5 * BLK
+// doubles.
+template <typename real, int EQ, int DIM, int N, int FLUX, int BLK, bool SLOTS = false>
 __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &a, long e0, long slot, double *dsmem)
 {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
@@ -855,7 +901,8 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
                                          dsmem + 2 * BLK, a.alpha_raw_out, a.features);
         }
     }
-    block_max_lanes<BLK>(sp, dsmem, a.partials + slot);
+    if constexpr (SLOTS) block_max_lanes<BLK, true>(sp, dsmem, a.partials + slot % DT_SLOTS);
+    else block_max_lanes<BLK>(sp, dsmem, a.partials + slot);
 }
 
 template <typename real, int EQ, int DIM, int N, int FLUX>
@@ -864,7 +911,7 @@ __global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     constexpr int TB = tile_block<NP>();
     __shared__ double dsmem[5 * TB];
-    interface_tile<real, EQ, DIM, N, FLUX, TB>(t, a, (long)blockIdx.x * (TB / NP), blockIdx.x, dsmem);
+    interface_tile<real, EQ, DIM, N, FLUX, TB, true>(t, a, (long)blockIdx.x * (TB / NP), blockIdx.x, dsmem);
 }
 
 // dt = cfl / ((N+1) m) from the global wave-speed maximum m (MHD: m = c_h and
@@ -983,6 +1030,31 @@ static __global__ void __launch_bounds__(FINAL_BLOCK) k_dt_final(const Tables t,
         for (int w = 1; w < FINAL_BLOCK / 64; ++w) m = fmax(m, red[w]);
         finish_dt(t, m, is_mhd, dt);
     }
+}
+
+// dt of the pipelined step from the DT_SLOTS merged maxima, which it leaves
+// at zero for the next interface phase
+static __global__ void __launch_bounds__(DT_SLOTS) k_dt_slots(const Tables t, double *slots, int is_mhd, double *dt)
+{
+    __shared__ double red[DT_SLOTS / 64];
+    const int tid = threadIdx.x;
+    double mx = slots[tid];
+    slots[tid] = 0.0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double m = red[0];
+        for (int w = 1; w < DT_SLOTS / 64; ++w) m = fmax(m, red[w]);
+        finish_dt(t, m, is_mhd, dt);
+    }
+}
+
+static __global__ void k_zero(double *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
 }
 
 // ---------------------------------------------------------------- K8: modal indicator
@@ -1123,7 +1195,10 @@ hipError_t launch_local(const Tables &t, const StepPtrs &p, hipStream_t s)
         else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4>), dim3(grid), dim3(TB), 0, s, t, p);
         break;
     case 5: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 5>), dim3(grid), dim3(TB), 0, s, t, p); break;
-    case 6: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6>), dim3(grid), dim3(TB), 0, s, t, p); break;
+    case 6:
+        if (t.tableau == 2) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6, 2>), dim3(grid), dim3(TB), 0, s, t, p);
+        else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6>), dim3(grid), dim3(TB), 0, s, t, p);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1138,8 +1213,7 @@ hipError_t launch_interface(const Tables &t, const StepPtrs &p, hipStream_t s)
     const int grid = (t.nelem + EPB - 1) / EPB;
     hipLaunchKernelGGL((k_interface<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(TB), 0, s, t, p);
     if (p.dt_out != nullptr)
-        hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(FINAL_BLOCK), 0, s, t, (const double *)p.partials, grid,
-                           EQ == EQ_MHD ? 1 : 0, p.dt_out);
+        hipLaunchKernelGGL(k_dt_slots, dim3(1), dim3(DT_SLOTS), 0, s, t, p.partials, EQ == EQ_MHD ? 1 : 0, p.dt_out);
     return hipGetLastError();
 }
 
@@ -1155,7 +1229,7 @@ hipError_t launch_run(const Tables &t, const StepPtrs &p, double *dt, int nsteps
     case 3: CRK_RUN(3, 0); break;
     case 4: if (t.tableau == 1) CRK_RUN(4, 1); else CRK_RUN(4, 0); break;
     case 5: CRK_RUN(5, 0); break;
-    case 6: CRK_RUN(6, 0); break;
+    case 6: if (t.tableau == 2) CRK_RUN(6, 2); else CRK_RUN(6, 0); break;
     default: return hipErrorInvalidValue;
     }
 #undef CRK_RUN
@@ -1181,6 +1255,12 @@ hipError_t launch_indicator(const Tables &t, const void *u, double *araw, double
     hipLaunchKernelGGL((k_indicator<real, DIM, N>), dim3(grid), dim3(BLOCK), 0, s, t, u, araw, features);
     if (alpha)
         hipLaunchKernelGGL(k_smooth, dim3((t.nelem + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, t, (const double *)araw, alpha);
+    return hipGetLastError();
+}
+
+inline hipError_t launch_zero(double *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -85,6 +85,44 @@ def test_euler1d_step_parity(orc, N, vol):
     assert _rel(_gpu_step(s, u, dt), ref) <= TOL64
 
 
+def _dense6():
+    """a six-stage explicit tableau with every strictly lower entry non-zero
+    (consistent rows, no particular order: it only exercises the general
+    stage bookkeeping)"""
+    A = [[0.0] * 6 for _ in range(6)]
+    c = [0.0, 0.2, 0.3, 0.6, 0.8, 1.0]
+    for k in range(1, 6):
+        w = [float(j + 1) for j in range(k)]
+        A[k][:k] = [c[k] * x / sum(w) for x in w]
+    return A, [0.1, 0.15, 0.2, 0.2, 0.2, 0.15]
+
+
+SSPRK3 = ([[0, 0, 0], [1, 0, 0], [0.25, 0.25, 0]], [1 / 6, 1 / 6, 2 / 3])
+
+
+@pytest.mark.parametrize("case", ["dense6_N3", "butcher6_N3", "rk4_N4", "ssprk3_N2", "dense6_mhd_N2"])
+def test_tableau_classes_parity(orc, case):
+    """the kernels specialised on the sparsity of A (classical RK4, Butcher's
+    six-stage pattern, general) against the oracle, each on a degree it is not
+    the default for"""
+    tab = {"dense6": _dense6(), "butcher6": (orc.RK5_A, orc.RK5_B), "rk4": (orc.RK4_A, orc.RK4_B),
+           "ssprk3": SSPRK3}
+    name, deg = case.split("_N")
+    mhd = name.endswith("_mhd")
+    A, b = tab[name.replace("_mhd", "")]
+    kw = dict(dim=2, nx=9, ny=7, N=int(deg), A=A, b=b)
+    kw.update(dict(eq=orc.MHD, gamma=5.0 / 3.0, vol_flux=3) if mhd else dict(vol_flux=2))
+    p, s = _pair(orc, **kw)
+    u = _state(orc, p, seed=41)
+    if mhd:
+        p.ch = orc.compute_ch(p, u)
+    dt = orc.compute_dt(p, u)
+    ref, _ = orc.crk_step(p, u, dt)
+    got = _gpu_step(s, u, dt, ch=p.ch)
+    print(f"{case}: rel={_rel(got, ref):.2e}")
+    assert _rel(got, ref) <= TOL64
+
+
 @pytest.mark.parametrize("dim,N,vol", [(2, 3, 1), (2, 4, 2), (1, 3, 2)])
 def test_dt_parity(orc, dim, N, vol):
     p, s = _pair(orc, dim=dim, nx=13, ny=11, N=N, vol_flux=vol)
@@ -333,6 +371,22 @@ def test_full_size_khi_parity(orc):
     got = out.cpu().numpy()
     print(f"full size rel={_rel(got, ref):.2e}, alpha>0 in {np.count_nonzero(alpha)} elements")
     assert _rel(got, ref) <= TOL64
+    # the launches the benchmark times: prepare + pipelined advance, whose
+    # interface phase merges the wave-speed maxima of 16384 workgroups into
+    # shared slots (several per slot, from every XCD)
+    b = [ug.clone(), s.new_state()]
+    dtp = s.new_dt()
+    s.prepare(b[0], dtp)
+    s.advance(b[0], b[1], dtp)
+    torch.cuda.synchronize()
+    assert _rel(b[1].cpu().numpy(), ref) <= TOL64
+    dnew = orc.compute_dt(p, ref)
+    assert abs(dtp[0].item() - dnew) <= 1e-14 * dnew
+    assert torch.equal(dtp, s.compute_dt(b[1]))
+    for n in range(2):          # the slots are back at zero for the next steps
+        s.advance(b[(n + 1) % 2], b[n % 2], dtp)
+        torch.cuda.synchronize()
+        assert torch.equal(dtp, s.compute_dt(b[n % 2]))
 
 
 @pytest.mark.parametrize("case", ["khi_blend", "euler1d", "mhd"])
