@@ -66,17 +66,25 @@ __global__ void __launch_bounds__(BLK) k_batch_local(const BatchProblem *probs, 
     }
 }
 
-template <typename real, int FLUX, int BLK>
-__global__ void __launch_bounds__(BLK) k_batch_interface(const BatchProblem *probs, const BatchTile *tiles, int ntiles,
-                                                         int dir)
+// Interface phase over the tiles [t0, t1) of one degree, split and
+// scheduled as the local phase.  The tile maxima go to partials[tile].
+template <typename real, int FLUX, int BLK, int NDEG, bool PERSIST>
+__global__ void __launch_bounds__(BLK) k_batch_interface(const BatchProblem *probs, const BatchTile *tiles, int t0,
+                                                         int t1, int dir)
 {
     __shared__ double dsmem[5 * BLK];
-    for (int it = blockIdx.x; it < ntiles; it += gridDim.x) {
+    auto tile = [&](int it) {
         const BatchTile tl = tiles[it];
         const BatchProblem &bp = probs[tl.prob];
-        if (bp.t.N == 3) interface_tile<real, EQ_EULER, 2, 3, FLUX, BLK>(bp.t, bp.p[dir], tl.e0, it, dsmem);
-        else interface_tile<real, EQ_EULER, 2, 4, FLUX, BLK>(bp.t, bp.p[dir], tl.e0, it, dsmem);
-        __syncthreads();
+        interface_tile<real, EQ_EULER, 2, NDEG, FLUX, BLK>(bp.t, bp.p[dir], tl.e0, it, dsmem);
+    };
+    if constexpr (PERSIST) {
+        for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
+            tile(it);
+            __syncthreads();
+        }
+    } else {
+        tile(t0 + blockIdx.x);
     }
 }
 
@@ -179,25 +187,24 @@ hipError_t launch_phase(const crk_batch *b, int kind, int dir, hipStream_t s)
     double *parts = (double *)(b->ws + b->off_parts);
     const int nt = (int)b->tiles.size();
     const int g = b->grid > 0 && b->grid < nt ? b->grid : nt;
-    if (kind == 0) {
-        const int n3 = b->ntiles3, n4 = nt - n3;
-        if (b->grid > 0) {
-            if (n3 > 0)
-                hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 3, true>), dim3(b->grid < n3 ? b->grid : n3),
-                                   dim3(BLK), 0, s, pr, tl, 0, n3, dir);
-            if (n4 > 0)
-                hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 4, true>), dim3(b->grid < n4 ? b->grid : n4),
-                                   dim3(BLK), 0, s, pr, tl, n3, nt, dir);
-        } else {
-            if (n3 > 0)
-                hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 3, false>), dim3(n3), dim3(BLK), 0, s, pr, tl, 0,
-                                   n3, dir);
-            if (n4 > 0)
-                hipLaunchKernelGGL((k_batch_local<real, FLUX, BLK, 4, false>), dim3(n4), dim3(BLK), 0, s, pr, tl, n3,
-                                   nt, dir);
-        }
-    } else if (kind == 1) hipLaunchKernelGGL((k_batch_interface<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir);
+    const int n3 = b->ntiles3, n4 = nt - n3;
+    const bool pers = b->grid > 0;
+    auto grid_of = [&](int n) { return dim3(pers && b->grid < n ? b->grid : n); };
+    // one launch per degree and phase: the degree-3 tiles [0, n3), then the degree-4 ones [n3, nt)
+#define CRK_BATCH_PHASE(K)                                                                                  \
+    do {                                                                                                    \
+        if (pers) {                                                                                         \
+            if (n3 > 0) hipLaunchKernelGGL((K<real, FLUX, BLK, 3, true>), grid_of(n3), dim3(BLK), 0, s, pr, tl, 0, n3, dir);  \
+            if (n4 > 0) hipLaunchKernelGGL((K<real, FLUX, BLK, 4, true>), grid_of(n4), dim3(BLK), 0, s, pr, tl, n3, nt, dir); \
+        } else {                                                                                            \
+            if (n3 > 0) hipLaunchKernelGGL((K<real, FLUX, BLK, 3, false>), dim3(n3), dim3(BLK), 0, s, pr, tl, 0, n3, dir);    \
+            if (n4 > 0) hipLaunchKernelGGL((K<real, FLUX, BLK, 4, false>), dim3(n4), dim3(BLK), 0, s, pr, tl, n3, nt, dir);   \
+        }                                                                                                   \
+    } while (0)
+    if (kind == 0) CRK_BATCH_PHASE(k_batch_local);
+    else if (kind == 1) CRK_BATCH_PHASE(k_batch_interface);
     else hipLaunchKernelGGL((k_batch_speed<real, FLUX, BLK>), dim3(g), dim3(BLK), 0, s, pr, tl, nt, dir, parts);
+#undef CRK_BATCH_PHASE
     if (kind != 0) hipLaunchKernelGGL(k_batch_dt, dim3(b->nprob), dim3(256), 0, s, pr, (const double *)parts, b->dt);
     return hipGetLastError();
 }
