@@ -27,6 +27,19 @@ template <int NP>
 constexpr int tile_block() { return 64 % NP == 0 ? CRK_WAVE_TILE : BLOCK; }
 inline int tile_block_rt(int np) { return 64 % np == 0 ? CRK_WAVE_TILE : BLOCK; }
 
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the
+// eight XCDs (b -> XCD b mod 8), each with its own L2.  Giving XCD x the
+// contiguous tile range [x G/8, (x+1) G/8) (plus one of the G mod 8 spare
+// tiles) keeps horizontally adjacent element tiles, which share the cache
+// lines of their face data, on one XCD and close in time.  A bijection of
+// [0, G) for every G.
+constexpr int NXCD = 8;
+__device__ __forceinline__ long xcd_tile(long b, long G)
+{
+    const long x = b % NXCD, q = G / NXCD, r = G % NXCD;
+    return x * q + (x < r ? x : r) + b / NXCD;
+}
+
 // Everything a kernel needs besides its pointers; passed by value.
 struct Tables {
     int dim, nx, ny, N, M, nelem, nnode, nface;  // nface = nodes per face
@@ -653,7 +666,7 @@ __global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     constexpr int TB = tile_block<NP>();
     __shared__ real smem[LocalShape<real, EQ, DIM, N, FLUX>::slots * TB];
-    local_tile<real, EQ, DIM, N, FLUX, S, TB, TAB>(t, a, (long)blockIdx.x * (TB / NP), smem);
+    local_tile<real, EQ, DIM, N, FLUX, S, TB, TAB>(t, a, xcd_tile(blockIdx.x, gridDim.x) * (TB / NP), smem);
 }
 
 // ---------------------------------------------------------------- K8 helper: modal indicator
@@ -911,7 +924,7 @@ __global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     constexpr int TB = tile_block<NP>();
     __shared__ double dsmem[5 * TB];
-    interface_tile<real, EQ, DIM, N, FLUX, TB, true>(t, a, (long)blockIdx.x * (TB / NP), blockIdx.x, dsmem);
+    interface_tile<real, EQ, DIM, N, FLUX, TB, true>(t, a, xcd_tile(blockIdx.x, gridDim.x) * (TB / NP), blockIdx.x, dsmem);
 }
 
 // dt = cfl / ((N+1) m) from the global wave-speed maximum m (MHD: m = c_h and
