@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(BLK) k_batch_local(const BatchProblem *probs, 
             __syncthreads();
         }
     } else {
-        tile(t0 + blockIdx.x, threadIdx.x);      // the grid is exactly the tile count
+        tile(t0 + (int)xcd_tile(blockIdx.x, gridDim.x), threadIdx.x);   // the grid is exactly the tile count
     }
 }
 
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(BLK) k_batch_interface(const BatchProblem *pro
             __syncthreads();
         }
     } else {
-        tile(t0 + blockIdx.x);
+        tile(t0 + (int)xcd_tile(blockIdx.x, gridDim.x));
     }
 }
 
