@@ -520,7 +520,8 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
             // the line) and the face terms in the same branch
             if (onface[d]) {
                 real fp[M];
-                Phys::phys(d, nd, fp, ctx);
+                if constexpr (EQ == EQ_EULER) Phys::phys_cons(d, us, nd, fp, ctx);
+                else Phys::phys(d, nd, fp, ctx);
                 const real gp = oaf[d] * bi * real(0.5), gw = bi * cF[d];
 #pragma unroll
                 for (int v = 0; v < M; ++v) {

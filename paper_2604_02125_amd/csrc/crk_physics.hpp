@@ -116,7 +116,22 @@ struct EulerP {
     template <bool LOGS = true>
     __device__ __forceinline__ static void fields(const real *u, real *nd, const Ctx<real> &c)
     {
-        const real rho = u[0], irho = real(1) / rho;
+        const real rho = u[0], irho = rcp_nr(rho);
+        if constexpr (HALF) {
+            // halved fields straight from u: scaling by 1/2 is exact, so these
+            // equal the halves of v, p and E/rho bit for bit
+            const real h = real(0.5), ih = h * irho;
+            real s = real(0);   // = |m|^2 / (2 rho)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                nd[1 + k] = u[1 + k] * ih;
+                s += u[1 + k] * nd[1 + k];
+            }
+            nd[0] = h * rho;
+            nd[P] = (h * c.gm1) * (u[DIM + 1] - s);
+            nd[DIM + 2] = u[DIM + 1] * ih;
+            return;
+        }
         real ke = real(0), v[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -124,26 +139,17 @@ struct EulerP {
             ke += u[1 + k] * v[k];
         }
         const real p = c.gm1 * (u[DIM + 1] - real(0.5) * ke);
-        if constexpr (HALF) {
-            const real h = real(0.5);
-            nd[0] = h * rho;
+        nd[0] = rho;
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) nd[1 + k] = h * v[k];
-            nd[P] = h * p;
-            nd[DIM + 2] = h * (u[DIM + 1] * irho);
-        } else {
-            nd[0] = rho;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) nd[1 + k] = v[k];
-            nd[P] = p;
-            if constexpr (FLUX == VOL_CENTRAL) {
-                nd[DIM + 2] = u[DIM + 1];
-            } else if constexpr (LOGS) {
-                const real beta = rho / p;
-                nd[DIM + 2] = dlog(rho);
-                nd[DIM + 3] = beta;
-                nd[DIM + 4] = dlog(beta);
-            }
+        for (int k = 0; k < DIM; ++k) nd[1 + k] = v[k];
+        nd[P] = p;
+        if constexpr (FLUX == VOL_CENTRAL) {
+            nd[DIM + 2] = u[DIM + 1];
+        } else if constexpr (LOGS) {
+            const real beta = rho * rcp_nr(p);
+            nd[DIM + 2] = dlog(rho);
+            nd[DIM + 3] = beta;
+            nd[DIM + 4] = dlog(beta);
         }
     }
     __device__ __forceinline__ static void node(const real *u, real *nd, const Ctx<real> &c) { fields<true>(u, nd, c); }
@@ -185,6 +191,19 @@ struct EulerP {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) f[1 + k] = m * v[k] + (k == d ? p : real(0));
         f[DIM + 1] = (E + p) * v[d];
+    }
+
+    // the same flux from the conserved state u and its fields: the momentum
+    // and energy are taken as they are, which saves the products that
+    // rebuild them from the fields
+    __device__ __forceinline__ static void phys_cons(int d, const real *u, const real *nd, real *f, const Ctx<real> &c)
+    {
+        const real s = HALF ? real(2) : real(1);
+        const real vd = s * nd[1 + d], p = s * nd[P];
+        f[0] = u[1 + d];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) f[1 + k] = (k == d) ? u[1 + k] * vd + p : u[1 + k] * vd;
+        f[DIM + 1] = (u[DIM + 1] + p) * vd;
     }
 
     __device__ __forceinline__ static real speed(int d, const real *nd, const Ctx<real> &c)
