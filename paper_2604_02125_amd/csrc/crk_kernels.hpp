@@ -418,10 +418,11 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     // (L: interior subcell FV update).  For MHD the own non-conservative
     // trace term and the own half of 1/2 B(u^n)(g(U^-) + g(U^+)) enter W the
     // same way; the normal field and psi of U are kept and published.
-    real Z[S][M];     // Z[k] = sum_{j<k} a_kj R^(j)
+    real Z[S][M];     // Z[k] = sum_{j<k} a_kj R^(j) (TAB 1: Z[k] = R^(k-1), a_{k,k-1} enters with dt)
     real W[M], P[DIM][M];
     real UB[DIM], Upsi = real(0);   // MHD: time averages of B_d and psi
     real hl[DIM], sw[DIM], oaf[DIM], cF[DIM], cU = real(0);
+    real ohl[DIM], oafh[DIM];       // oaf hl and oaf / 2, the per-stage factors of P_d
     real oma = real(1);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
@@ -438,20 +439,23 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         hl[d] = onface[d] ? (side[d] ? real(0.5) : real(-0.5)) * llds[d * BLK + tid] : real(0);
         oaf[d] = real(1);
         cF[d] = real(0);
+        ohl[d] = hl[d];
+        oafh[d] = real(0.5);
     }
 
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         real us[M];
+        const real cz = (TAB == 1 && i > 0) ? rdt * real(t.A[i][i > 0 ? i - 1 : 0]) : rdt;
 #pragma unroll
-        for (int v = 0; v < M; ++v) us[v] = (i == 0) ? un[v] : un[v] - rdt * Z[i][v];
+        for (int v = 0; v < M; ++v) us[v] = (i == 0) ? un[v] : un[v] - cz * Z[i][v];
         const real bi = real(t.b[i]);
         if (i > 0) {
             // the u^(i) terms of P_d and W (those of u^(0) = u^n follow the
             // first barrier, where the blending factors are known)
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-                const real g = oaf[d] * bi * hl[d];
+                const real g = bi * ohl[d];
 #pragma unroll
                 for (int v = 0; v < M; ++v) P[d][v] += g * us[v];
             }
@@ -478,9 +482,11 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                 const real af = (blend && valid && onface[d])
                                     ? real(0.5) * (alpha + alds[le * NA + 1 + 2 * d + side[d]]) : real(0);
                 oaf[d] = real(1) - af;
-                cF[d] = sw[d] * (real(0.5) * oaf[d] - oma);
-                cU += sw[d] * oaf[d] * hl[d];
-                const real g = oaf[d] * bi * hl[d];
+                oafh[d] = real(0.5) * oaf[d];
+                ohl[d] = oaf[d] * hl[d];
+                cF[d] = sw[d] * (oafh[d] - oma);
+                cU += sw[d] * ohl[d];
+                const real g = bi * ohl[d];
 #pragma unroll
                 for (int v = 0; v < M; ++v) P[d][v] += g * un[v];
             }
@@ -522,7 +528,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                 real fp[M];
                 if constexpr (EQ == EQ_EULER) Phys::phys_cons(d, us, nd, fp, ctx);
                 else Phys::phys(d, nd, fp, ctx);
-                const real gp = oaf[d] * bi * real(0.5), gw = bi * cF[d];
+                const real gp = bi * oafh[d], gw = bi * cF[d];
 #pragma unroll
                 for (int v = 0; v < M; ++v) {
                     R[v] += Ddiag[d] * fp[v];
@@ -609,9 +615,8 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         if constexpr (TAB == 1) {
             // classical RK4: only a_{i+1,i} is non-zero
             if (i + 1 < S) {
-                const real a1 = real(t.A[i + 1][i]);
 #pragma unroll
-                for (int v = 0; v < M; ++v) Z[i + 1][v] = a1 * R[v];
+                for (int v = 0; v < M; ++v) Z[i + 1][v] = R[v];
             }
         } else {
 #pragma unroll
