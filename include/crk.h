@@ -253,9 +253,10 @@ crk_status crk_set_mlp(crk_solver *s, const uint16_t *theta_bf16, const float *f
  * Many independent periodic 2D Euler meshes (degree 3 with classical RK4,
  * degree 4 with Butcher's RK5, one precision, Kennedy-Gruber or Ranocha
  * volume flux, no limiter) advanced together by pipelined steps.  The
- * element tiles of all problems form one work list walked by persistent
- * kernels: one launch per phase, whatever the mix of degrees; each problem
- * has its own CFL time step.  Each problem i occupies the values
+ * element tiles of all problems form one work list (degree-3 tiles first);
+ * each phase is one launch per degree over the tiles of that degree, with
+ * one workgroup per tile or a fixed grid of persistent workgroups (tuning);
+ * each problem has its own CFL time step.  Each problem i occupies the values
  * [offsets[i], offsets[i+1]) of a state buffer, laid out as u[v][e][node]
  * of that problem. */
 typedef struct crk_batch crk_batch;

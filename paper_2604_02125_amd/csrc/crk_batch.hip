@@ -1,10 +1,10 @@
 // crk_batch.hip -- many independent periodic 2D Euler meshes of uneven size
 // and degree (N = 3 with classical RK4, N = 4 with Butcher's RK5) advanced
-// together.  A host-built work list of (problem, element tile) items is
-// walked by persistent kernels: one launch per phase covers every problem
-// whatever its degree; the CFL time step is reduced per problem.  Two
-// pipelined steps (u0 -> u1 -> u0) can be captured once into a HIP graph and
-// replayed.
+// together.  A host-built work list of (problem, element tile) items, the
+// degree-3 tiles first, is covered per phase by one launch per degree (one
+// workgroup per tile, or persistent workgroups walking the tiles); the CFL
+// time step is reduced per problem.  Two pipelined steps (u0 -> u1 -> u0)
+// can be captured once into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
