@@ -13,7 +13,7 @@ The same JSON line carries the variants (FP32; the batch of 512 uneven
 problems replayed as a HIP graph; Kelvin-Helmholtz 512^2 with the learned
 indicator; GLM-MHD Orszag-Tang; the 1D density wave), each with its relative
 L2 error against the FP64 CPU oracle stepped from the same initial state.
-``--gpus`` above 1 is rejected: this build runs on a single GPU.
+``--gpus`` above 1 is rejected: the path is measured on a single GPU (it is not sharded).
 """
 from __future__ import annotations
 
@@ -330,7 +330,7 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB five times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (no multi-GPU path in this build); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the path is not sharded across GPUs; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
