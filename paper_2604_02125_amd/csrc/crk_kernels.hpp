@@ -795,10 +795,11 @@ __device__ __forceinline__ void block_max_lanes(double v, double *red, double *s
 }
 
 // Slots of the pipelined step's wave-speed maximum: interface-phase
-// workgroup b merges its maximum into slot b mod DT_SLOTS; k_dt_slots reads
-// every slot once (one load per lane), puts it back to zero for the next
-// step and finishes dt.  Far fewer loads than one partial per workgroup.
-constexpr int DT_SLOTS = 1024;
+// workgroup b merges its maximum into slot b mod DT_SLOTS; k_dt_slots, one
+// wavefront, reads every slot once (four loads per lane, issued together),
+// puts it back to zero for the next step and finishes dt.  Far fewer loads
+// than one partial per workgroup.
+constexpr int DT_SLOTS = 256;
 
 // ---------------------------------------------------------------- K3: interface + final update
 // One lane per node; the face-node lanes apply the interface corrections.
@@ -1053,21 +1054,22 @@ static __global__ void __launch_bounds__(FINAL_BLOCK) k_dt_final(const Tables t,
 
 // dt of the pipelined step from the DT_SLOTS merged maxima, which it leaves
 // at zero for the next interface phase
-static __global__ void __launch_bounds__(DT_SLOTS) k_dt_slots(const Tables t, double *slots, int is_mhd, double *dt)
+static __global__ void __launch_bounds__(64) k_dt_slots(const Tables t, double *slots, int is_mhd, double *dt)
 {
-    __shared__ double red[DT_SLOTS / 64];
+    // one wavefront: DT_SLOTS / 64 loads per lane in flight together, then a butterfly
     const int tid = threadIdx.x;
-    double mx = slots[tid];
-    slots[tid] = 0.0;
+    double v[DT_SLOTS / 64];
+#pragma unroll
+    for (int j = 0; j < DT_SLOTS / 64; ++j) v[j] = slots[j * 64 + tid];
+    double mx = 0.0;
+#pragma unroll
+    for (int j = 0; j < DT_SLOTS / 64; ++j) {
+        mx = fmax(mx, v[j]);
+        slots[j * 64 + tid] = 0.0;
+    }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) mx = fmax(mx, __shfl_xor(mx, m, 64));
-    if ((tid & 63) == 0) red[tid >> 6] = mx;
-    __syncthreads();
-    if (tid == 0) {
-        double m = red[0];
-        for (int w = 1; w < DT_SLOTS / 64; ++w) m = fmax(m, red[w]);
-        finish_dt(t, m, is_mhd, dt);
-    }
+    if (tid == 0) finish_dt(t, mx, is_mhd, dt);
 }
 
 static __global__ void k_zero(double *p, int n)
@@ -1232,7 +1234,7 @@ hipError_t launch_interface(const Tables &t, const StepPtrs &p, hipStream_t s)
     const int grid = (t.nelem + EPB - 1) / EPB;
     hipLaunchKernelGGL((k_interface<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(TB), 0, s, t, p);
     if (p.dt_out != nullptr)
-        hipLaunchKernelGGL(k_dt_slots, dim3(1), dim3(DT_SLOTS), 0, s, t, p.partials, EQ == EQ_MHD ? 1 : 0, p.dt_out);
+        hipLaunchKernelGGL(k_dt_slots, dim3(1), dim3(64), 0, s, t, p.partials, EQ == EQ_MHD ? 1 : 0, p.dt_out);
     return hipGetLastError();
 }
 
