@@ -56,6 +56,26 @@ def test_argument_validation():
     assert _create(precision=7) == -1
 
 
+def _tableau(A, b):
+    s = len(b)
+    Ac = (C.c_double * (s * s))(*[float(x) for row in A for x in row])
+    bc = (C.c_double * s)(*[float(x) for x in b])
+    return dict(stages=s, A=C.cast(Ac, C.POINTER(C.c_double)), b=C.cast(bc, C.POINTER(C.c_double))), (Ac, bc)
+
+
+def test_limits_and_tableau_validation():
+    # node count beyond 32-bit indexing: rejected before anything is sized
+    assert _create(nx=16384, ny=16384) == -1
+    assert "too large" in crk.lib().crk_last_error().decode()
+    # tableaus: 1..6 stages, strictly lower-triangular A
+    kw, keep = _tableau([[0, 0, 0], [1, 0, 0], [0.25, 0.25, 0]], [1 / 6, 1 / 6, 2 / 3])
+    assert _create(**kw) == 0
+    kw, keep = _tableau([[0, 0], [1, 0.5]], [0.5, 0.5])
+    assert _create(**kw) == -1
+    kw, keep = _tableau([[0] * 7 for _ in range(7)], [1 / 7] * 7)
+    assert _create(**kw) == -2
+
+
 def test_calls_without_workspace_fail_cleanly():
     m = crk.MeshDesc(2, 4, 4, 0.0, 1.0, 0.0, 1.0, 3, crk.CRK_EULER, 1.4, crk.FP64)
     sc = crk.SchemeDesc()
@@ -72,4 +92,9 @@ def test_calls_without_workspace_fail_cleanly():
     assert crk.lib().crk_set_workspace(h, C.c_void_p(256), 16) == -1      # too small
     nb = C.c_size_t()
     assert crk.lib().crk_workspace_bytes(h, C.byref(nb)) == 0 and nb.value > 0
+    # a (never dereferenced) workspace address: pipelined steps still need crk_prepare first
+    assert crk.lib().crk_set_workspace(h, C.c_void_p(1 << 20), nb.value) == 0
+    assert crk.lib().crk_advance(h, C.c_void_p(256), C.c_void_p(4096), C.c_void_p(768), 3, None) == -6
+    assert crk.lib().crk_run(h, C.c_void_p(256), C.c_void_p(4096), C.c_void_p(768), 5, None) == -6
+    assert crk.lib().crk_advance(h, C.c_void_p(256), C.c_void_p(4096), C.c_void_p(768), 4, None) == -1
     crk.lib().crk_destroy(h)
