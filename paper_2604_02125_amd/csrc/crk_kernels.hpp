@@ -257,10 +257,12 @@ struct LocalShape {
     static constexpr int NPRIM = SYM ? (n1 - 1) / 2 : 0;           // rotations whose mirror comes from LDS
     static constexpr int KSELF = (SYM && n1 % 2 == 0) ? n1 / 2 : 0;  // self-mirrored rotation, evaluated directly
     static constexpr int NX = SYM ? DIM * NPRIM * Phys::M : 0;
-    // two more slots carry the blending coefficients of each element and of
-    // its face neighbours ((2 DIM + 1) values per element, N + 1 >= 2), DIM
-    // slots the Rusanov speed of the faces through each node
-    static constexpr int slots = Phys::NF + NX + 2 + DIM;
+    // ASL slots carry the blending coefficients of each element and of its
+    // face neighbours ((2 DIM + 1) values per element of NP lanes), DIM slots
+    // the Rusanov speed of the faces through each node
+    static constexpr int NP = DIM == 2 ? n1 * n1 : n1;
+    static constexpr int ASL = (2 * DIM + 1 + NP - 1) / NP;
+    static constexpr int slots = Phys::NF + NX + ASL + DIM;
 };
 
 // One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
@@ -281,7 +283,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     real *lds = smem;                // [NF][BLK]
     real *xch = smem + NF * BLK;     // [NX][BLK]
     real *alds = xch + Shape::NX * BLK;   // [EPB][2 DIM + 1]
-    real *llds = alds + 2 * BLK;          // [DIM][BLK]
+    real *llds = alds + Shape::ASL * BLK; // [DIM][BLK]
     constexpr int NA = 2 * DIM + 1;
 
     const int tid = lane >= 0 ? lane : (int)threadIdx.x;   // (lane: see the batched local phase)
