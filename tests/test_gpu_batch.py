@@ -123,3 +123,39 @@ def test_batch_rejects_bad_input():
         crk.Batch([(4, 2)])           # degree 2 not in a batch
     with pytest.raises(crk.CrkError):
         crk.Batch([(4, 3)], volume_flux=crk.VOL_CENTRAL)
+
+
+def test_full_size_batch_sampled(orc):
+    """The benchmarked batch (512 problems, n ~ U{16..96}, N in {3, 4}, seed
+    20260402) in the benchmark's launch configuration (default tile shape,
+    two pipelined steps replayed from a HIP graph): sampled problems (the
+    largest of each degree, the smallest, and a seeded random few) against
+    the oracle after the two steps, state and dt."""
+    specs, rng = inputs.random_fourier_problems(512, seed=20260402)
+    b = crk.Batch(specs, volume_flux=crk.VOL_RANOCHA)
+    pick = set(np.random.default_rng(7).choice(len(specs), 6, replace=False).tolist())
+    for deg in (3, 4):
+        idx = [i for i, (n, N) in enumerate(specs) if N == deg]
+        pick.add(max(idx, key=lambda i: specs[i][0]))
+    pick.add(min(range(len(specs)), key=lambda i: specs[i][0]))
+    keep = {}
+    for i, (n, N) in enumerate(specs):
+        xi, _ = orc.gll(N)
+        u = inputs.random_fourier_state(rng, n, xi)
+        b.view(0, i).copy_(torch.tensor(u, dtype=b.dtype))
+        if i in pick:
+            keep[i] = u
+    torch.cuda.synchronize()
+    with torch.cuda.stream(b.stream):
+        b.prepare(0)
+        b.capture_graph()
+        b.launch_graph()
+    b.stream.synchronize()
+    for i, u in sorted(keep.items()):
+        n, N = specs[i]
+        p = orc.Problem(dim=2, nx=n, ny=n, N=N, vol_flux=orc.VOL_RANOCHA, nthreads=16)
+        ref = u
+        for _ in range(2):
+            ref, _ = orc.crk_step(p, ref, orc.compute_dt(p, ref))
+        assert _rel(b.view(0, i).cpu().numpy(), ref) <= 1e-12, (i, n, N)
+        assert abs(b.dt[2 * i].item() - orc.compute_dt(p, ref)) <= 1e-14 * b.dt[2 * i].item(), (i, n, N)
