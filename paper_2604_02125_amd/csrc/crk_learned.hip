@@ -292,13 +292,6 @@ __global__ void __launch_bounds__(256) k_mlp_alpha(const uint16_t *theta, const 
 #pragma unroll
     for (int i = 0; i < 4; ++i) { flo[i] = lo[4 * kq + i]; fhi[i] = hi[4 * kq + i]; }
 
-    // the features of the next tile are loaded while this one is computed
-    float xn[4];
-    {
-        const long e = wave * MX_TILE + col;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) xn[i] = e < nelem ? features[e * NIN + 4 * kq + i] : 0.f;
-    }
     for (long tile = wave; tile < ntiles; tile += nwaves) {
         const long e = tile * MX_TILE + col;
         const bool ev = e < nelem;
@@ -306,14 +299,8 @@ __global__ void __launch_bounds__(256) k_mlp_alpha(const uint16_t *theta, const 
         bool inside = true;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            x[i] = xn[i];
+            x[i] = ev ? features[e * NIN + 4 * kq + i] : 0.f;
             inside &= (x[i] >= flo[i]) && (x[i] <= fhi[i]);
-        }
-        {
-            const long en = (tile + nwaves) * MX_TILE + col;
-            const bool nv = tile + nwaves < ntiles && en < nelem;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) xn[i] = nv ? features[en * NIN + 4 * kq + i] : 0.f;
         }
         // the four lanes of an element (col, col + 16, col + 32, col + 48)
         inside = inside && __shfl_xor((int)inside, 16) && __shfl_xor((int)inside, 32);
