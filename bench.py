@@ -36,10 +36,10 @@ PEAK_FP32_TFLOPS = 157.3
 # calibration) and FP64 FLOPs = SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes; valid only
 # for the kernel sources whose digest is recorded with them.
 MEASURED_TRAFFIC = {
-    ("khi256", "fp64"): {"sources_sha256": "44f2becc92f26a3bdb15a2e13cc3a025b75b5ebecbc60e3bf3f4a87b106e568e",
+    ("khi256", "fp64"): {"sources_sha256": "bdf0fe883d6601bf283d4bf0f8fbc347d64d6c1bdcb33e2060a174e0341ead46",
                          "bytes": (2.0 * 20932.2 + 1.0 * 66048.0) * 1024,
                          "fp64_flops": 16465920.0 * 64},
-    ("khi256_ranocha", "fp64"): {"sources_sha256": "44f2becc92f26a3bdb15a2e13cc3a025b75b5ebecbc60e3bf3f4a87b106e568e",
+    ("khi256_ranocha", "fp64"): {"sources_sha256": "bdf0fe883d6601bf283d4bf0f8fbc347d64d6c1bdcb33e2060a174e0341ead46",
                                  "bytes": (2.0 * 21026.8 + 1.0 * 66048.0) * 1024,
                                  "fp64_flops": 43925504.0 * 64},
 }
