@@ -457,13 +457,18 @@ def test_full_size_mhd_parity(orc):
     assert rel <= TOL64
 
 
-@pytest.mark.parametrize("case", ["khi_blend", "euler1d", "mhd"])
+@pytest.mark.parametrize("case", ["khi_blend", "khi_blend_N2", "euler2d_N1", "euler1d", "mhd"])
 def test_pipelined_advance(orc, case):
     """crk_prepare + crk_advance (CFL reduction and indicator fused into the
     interface phase) against the oracle trajectory and against crk_step."""
     if case == "khi_blend":
         p, s = _pair(orc, dim=2, nx=24, ny=20, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=1,
                      limiter=orc.LIM_BLEND_MODAL)
+    elif case == "khi_blend_N2":
+        p, s = _pair(orc, dim=2, nx=27, ny=22, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=2, vol_flux=2,
+                     limiter=orc.LIM_BLEND_MODAL)
+    elif case == "euler2d_N1":
+        p, s = _pair(orc, dim=2, nx=29, ny=17, N=1, vol_flux=1)
     elif case == "euler1d":
         p, s = _pair(orc, dim=1, nx=37, N=3, vol_flux=2)
     else:
