@@ -77,6 +77,12 @@ def rel_l2(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
 
 
+def rel_linf(a, b):
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
 class Pipelined:
     """Pipelined stepping of one crk.Solver on torch's current stream."""
 
@@ -209,7 +215,9 @@ def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, thread
                         vol_flux=orc.VOL_KG if flux is None else flux, limiter=orc.LIM_BLEND_MODAL, nthreads=threads)
         oxi, _ = orc.gll(3)
         ref = oracle_steps(p, inputs.kelvin_helmholtz(n, n, oxi), err_steps)
-        out["l2_rel_error_vs_fp64_oracle"] = rel_l2(gpu_steps(s, u0, err_steps), ref)
+        got = gpu_steps(s, u0, err_steps)
+        out["l2_rel_error_vs_fp64_oracle"] = rel_l2(got, ref)
+        out["linf_rel_error_vs_fp64_oracle"] = rel_linf(got, ref)
         out["error_after_steps"] = err_steps
         if learned:
             s2 = crk.Solver(nx=n, ny=n, precision=precision, **KHI)
@@ -255,7 +263,7 @@ def variant_batch(crk, inputs, orc, precision, reps, err_sample=4):
         b.advance(0)
         b.advance(1)
     b.stream.synchronize()
-    num = den = 0.0
+    num = den = dmax = rmax = 0.0
     for i in range(err_sample):
         n, N = specs[i]
         p = orc.Problem(dim=2, nx=n, ny=n, N=N, vol_flux=orc.VOL_RANOCHA)
@@ -263,10 +271,12 @@ def variant_batch(crk, inputs, orc, precision, reps, err_sample=4):
         got = b.view(0, i).double().cpu().numpy()
         num += float(np.sum((got - ref) ** 2))
         den += float(np.sum(ref ** 2))
+        dmax = max(dmax, float(np.max(np.abs(got - ref))))
+        rmax = max(rmax, float(np.max(np.abs(ref))))
     return {"value": b.ndof / (ms * 1e-3), "unit": "DOF-updates/s", "ms_per_step": ms, "steps": 2 * reps,
             "problems": len(specs), "dofs": b.ndof, "tuning": {"block": b.tuning[0], "grid_per_cu": b.tuning[1]},
             "graph": "2 pipelined steps per replay",
-            "l2_rel_error_vs_fp64_oracle": float(np.sqrt(num / den)),
+            "l2_rel_error_vs_fp64_oracle": float(np.sqrt(num / den)), "linf_rel_error_vs_fp64_oracle": dmax / rmax,
             "error_after_steps": 2, "error_sample": f"first {err_sample} problems"}
 
 
@@ -282,9 +292,11 @@ def variant_mhd(crk, inputs, orc, precision, steps, warmup, threads):
     p = orc.Problem(dim=2, nx=n, ny=n, N=4, eq=orc.MHD, gamma=5.0 / 3.0, vol_flux=orc.VOL_DERIGS, nthreads=threads)
     oxi, _ = orc.gll(4)
     ref = oracle_steps(p, inputs.orszag_tang(n, n, oxi), 1)
+    got1 = gpu_steps(s, u0, 1)
     ndof = s.nelem * s.shape[2]
     return {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
-            "l2_rel_error_vs_fp64_oracle": rel_l2(gpu_steps(s, u0, 1), ref), "error_after_steps": 1}
+            "l2_rel_error_vs_fp64_oracle": rel_l2(got1, ref), "linf_rel_error_vs_fp64_oracle": rel_linf(got1, ref),
+            "error_after_steps": 1}
 
 
 def variant_wave1d(crk, inputs, orc):
@@ -313,7 +325,8 @@ def variant_wave1d(crk, inputs, orc):
     got = got_t.cpu().numpy()
     return {"value": 256 * 200 / el, "unit": "DOF-updates/s", "us_per_step": el / 200 * 1e6, "steps": 200,
             "launch": "one crk_run launch for the 200 steps",
-            "l2_rel_error_vs_fp64_oracle": rel_l2(got, ref), "error_after_steps": 200,
+            "l2_rel_error_vs_fp64_oracle": rel_l2(got, ref), "linf_rel_error_vs_fp64_oracle": rel_linf(got, ref),
+            "error_after_steps": 200,
             "max_velocity_deviation": float(np.max(np.abs(got[1] / got[0] - 0.1)))}
 
 
@@ -415,7 +428,8 @@ def main():
         v["mhd_ot192_fp64"] = variant_mhd(crk, inputs, orc, crk.FP64, 10, 2, threads)
         v["mhd_ot192_fp32"] = variant_mhd(crk, inputs, orc, crk.FP32, 10, 2, threads)
         v["density_wave_1d_fp64"] = variant_wave1d(crk, inputs, orc)
-        v["_note"] = ("l2_rel_error_vs_fp64_oracle = ||u_gpu - u_oracle||_2 / ||u_oracle||_2 over all values "
+        v["_note"] = ("l2_rel_error_vs_fp64_oracle = ||u_gpu - u_oracle||_2 / ||u_oracle||_2 and "
+                      "linf_rel_error_vs_fp64_oracle = max|u_gpu - u_oracle| / max|u_oracle| over all values "
                       "after error_after_steps steps from the same initial state (the FP64 rows are a "
                       "round-off check)")
         out["variants"] = v
