@@ -171,6 +171,21 @@ def check_admissible(solver, u, what):
         sys.exit(3)
 
 
+def conservation(pipe):
+    """FP64 diagnostics of the pipelined run so far against its initial state:
+    the relative drift of the total mass and the largest drift of any total
+    (relative to that total, or to the total mass where the total itself
+    vanishes; for MHD the Powell/GLM non-conservative terms move momentum,
+    energy, B and psi by design) and the relative change of the total
+    entropy (negative: Rusanov interfaces and blending dissipate)."""
+    d0 = pipe.s.diagnostics(pipe.u0).cpu().numpy()
+    d1 = pipe.s.diagnostics(pipe.state).cpu().numpy()
+    M = pipe.s.shape[0]
+    drift = max(abs(d1[v] - d0[v]) / max(abs(d0[v]), abs(d0[0])) for v in range(M))
+    return {"after_steps": pipe.n, "mass_rel_drift": float(abs(d1[0] - d0[0]) / abs(d0[0])),
+            "totals_max_rel_drift": float(drift), "entropy_rel_change": float((d1[M] - d0[M]) / abs(d0[M]))}
+
+
 def oracle_steps(prob, u0, nsteps):
     import oracle as orc
     u = u0
@@ -202,9 +217,11 @@ def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, thread
     pipe = Pipelined(s, u0)
     el, k2_ms = timed(pipe, steps, warmup, events=True)
     check_admissible(s, pipe.state, f"khi{n}")
+    cons = conservation(pipe)
     ndof = s.nelem * s.shape[2]
     out = {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
            "k_local_ms": k2_ms}
+    out["conservation"] = cons
     key = (f"khi{n}" + ("_ranocha" if flux == crk.VOL_RANOCHA else ""), "fp64" if precision == crk.FP64 else "fp32")
     rec = MEASURED_TRAFFIC.get(key)
     if rec and rec["sources_sha256"] == sources_digest() and flux is not None:
@@ -289,6 +306,7 @@ def variant_mhd(crk, inputs, orc, precision, steps, warmup, threads):
     pipe = Pipelined(s, u0)
     el, _ = timed(pipe, steps, warmup)
     check_admissible(s, pipe.state, "mhd")
+    cons = conservation(pipe)
     p = orc.Problem(dim=2, nx=n, ny=n, N=4, eq=orc.MHD, gamma=5.0 / 3.0, vol_flux=orc.VOL_DERIGS, nthreads=threads)
     oxi, _ = orc.gll(4)
     ref = oracle_steps(p, inputs.orszag_tang(n, n, oxi), 1)
@@ -296,7 +314,7 @@ def variant_mhd(crk, inputs, orc, precision, steps, warmup, threads):
     ndof = s.nelem * s.shape[2]
     return {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
             "l2_rel_error_vs_fp64_oracle": rel_l2(got1, ref), "linf_rel_error_vs_fp64_oracle": rel_linf(got1, ref),
-            "error_after_steps": 1}
+            "error_after_steps": 1, "conservation": cons}
 
 
 def variant_wave1d(crk, inputs, orc):
