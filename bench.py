@@ -203,7 +203,8 @@ def gpu_steps(solver, u0, nsteps):
     return pipe.state.double().cpu().numpy()
 
 
-def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, threads, learned=False, flux=None):
+def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, threads, learned=False, flux=None,
+                rough=0.0):
     import numpy as np
     cfg = dict(KHI)
     if flux is not None:
@@ -213,7 +214,11 @@ def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, thread
         net = crk.MLP.load(os.path.join(ROOT, "paper_2604_02125_amd", "mlp_indicator.npz"))
         net.bind(s)
     xi, _, _ = crk.reference_element(3)
+    # rough > 0: multiplicative noise of that size on the KHI state, so that
+    # the indicator blends (almost) every element
     u0 = inputs.kelvin_helmholtz(n, n, xi)
+    if rough:
+        u0 = inputs.perturb(u0, 17, rough)
     pipe = Pipelined(s, u0)
     el, k2_ms = timed(pipe, steps, warmup, events=True)
     check_admissible(s, pipe.state, f"khi{n}")
@@ -222,6 +227,7 @@ def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, thread
     out = {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
            "k_local_ms": k2_ms}
     out["conservation"] = cons
+    out["blended_element_fraction"] = float((s.indicator(pipe.state)[1] > 0).double().mean().item())
     key = (f"khi{n}" + ("_ranocha" if flux == crk.VOL_RANOCHA else ""), "fp64" if precision == crk.FP64 else "fp32")
     rec = MEASURED_TRAFFIC.get(key)
     if rec and rec["sources_sha256"] == sources_digest() and flux is not None:
@@ -231,7 +237,8 @@ def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, thread
         p = orc.Problem(dim=2, nx=n, ny=n, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3,
                         vol_flux=orc.VOL_KG if flux is None else flux, limiter=orc.LIM_BLEND_MODAL, nthreads=threads)
         oxi, _ = orc.gll(3)
-        ref = oracle_steps(p, inputs.kelvin_helmholtz(n, n, oxi), err_steps)
+        uo = inputs.kelvin_helmholtz(n, n, oxi)
+        ref = oracle_steps(p, inputs.perturb(uo, 17, rough) if rough else uo, err_steps)
         got = gpu_steps(s, u0, err_steps)
         out["l2_rel_error_vs_fp64_oracle"] = rel_l2(got, ref)
         out["linf_rel_error_vs_fp64_oracle"] = rel_linf(got, ref)
@@ -441,6 +448,8 @@ def main():
         # the same workload with the entropy-conservative Ranocha flux (log means)
         v["khi256_ranocha_fp64"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps, threads,
                                                flux=crk.VOL_RANOCHA)
+        v["khi256_blended_fp64"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps, threads,
+                                               rough=0.05)
         v["batch512_fp64"] = variant_batch(crk, inputs, orc, crk.FP64, 5)
         v["batch512_fp32"] = variant_batch(crk, inputs, orc, crk.FP32, 5)
         v["khi512_learned_fp64"] = variant_khi(crk, inputs, orc, 512, crk.FP64, 10, 2, args.err_steps, threads,
