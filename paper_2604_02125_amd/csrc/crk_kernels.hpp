@@ -262,7 +262,10 @@ struct LocalShape {
     // the Rusanov speed of the faces through each node
     static constexpr int NP = DIM == 2 ? n1 * n1 : n1;
     static constexpr int ASL = (2 * DIM + 1 + NP - 1) / NP;
-    static constexpr int slots = Phys::NF + NX + ASL + DIM;
+    // Euler, whole elements per wavefront: one slot for the sound speed of
+    // u^n, shared by the subcell fluxes of the blending limiter
+    static constexpr int CS = (EQ == EQ_EULER && 64 % NP == 0) ? 1 : 0;
+    static constexpr int slots = Phys::NF + NX + ASL + DIM + CS;
 };
 
 // One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
@@ -284,6 +287,8 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     real *xch = smem + NF * BLK;     // [NX][BLK]
     real *alds = xch + Shape::NX * BLK;   // [EPB][2 DIM + 1]
     real *llds = alds + Shape::ASL * BLK; // [DIM][BLK]
+    real *clds = llds + DIM * BLK;        // [CS][BLK]
+    constexpr bool CSH = Shape::CS > 0;
     constexpr int NA = 2 * DIM + 1;
 
     const int tid = lane >= 0 ? lane : (int)threadIdx.x;   // (lane: see the batched local phase)
@@ -500,6 +505,16 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         real R[M];
 #pragma unroll
         for (int v = 0; v < M; ++v) R[v] = real(0);
+        // sound speed of u^n for the subcell fluxes, once per node (the
+        // lanes of an element take the same branch)
+        real c_own = real(0);
+        if constexpr (CSH) {
+            if (i == 0 && blend && alpha > real(0)) {
+                c_own = Phys::sound(nd, ctx);
+                clds[tid] = c_own;
+                element_sync<NP>();
+            }
+        }
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             // directly evaluated rotations
@@ -576,7 +591,9 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 #pragma unroll
                 for (int v = 0; v < M; ++v) { fr[v] = real(0); fl[v] = real(0); }
                 Phys::phys(d, nd, fp, ctx);
-                const real lp = Phys::speed(d, nd, ctx);
+                real lp;
+                if constexpr (CSH) lp = Phys::vspeed(d, nd) + c_own;
+                else lp = Phys::speed(d, nd, ctx);
 #pragma unroll
                 for (int sgn = 0; sgn < 2; ++sgn) {
                     const int qd = sgn ? pd[d] + 1 : pd[d] - 1;
@@ -587,7 +604,10 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                     for (int f = 0; f < NF; ++f) ndq[f] = lds[f * BLK + base + q];
                     Phys::phys(d, ndq, fq, ctx);
                     Phys::cons(ndq, uq, ctx);
-                    const real lam = dmax(lp, Phys::speed(d, ndq, ctx));
+                    real lq;
+                    if constexpr (CSH) lq = Phys::vspeed(d, ndq) + clds[base + q];
+                    else lq = Phys::speed(d, ndq, ctx);
+                    const real lam = dmax(lp, lq);
 #pragma unroll
                     for (int v = 0; v < M; ++v) {
                         if (sgn) fr[v] = real(0.5) * (fp[v] + fq[v]) - real(0.5) * lam * (uq[v] - un[v]);

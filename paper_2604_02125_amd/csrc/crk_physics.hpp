@@ -208,8 +208,17 @@ struct EulerP {
 
     __device__ __forceinline__ static real speed(int d, const real *nd, const Ctx<real> &c)
     {
-        // (gamma p / rho) is the same with halved p and rho
-        return dabs((HALF ? real(2) : real(1)) * nd[1 + d]) + dsqrt(c.gamma * nd[P] / nd[0]);
+        return vspeed(d, nd) + sound(nd, c);
+    }
+    // the two parts of speed(): |v_d| and the sound speed ((gamma p / rho)
+    // is the same with halved p and rho)
+    __device__ __forceinline__ static real vspeed(int d, const real *nd)
+    {
+        return dabs((HALF ? real(2) : real(1)) * nd[1 + d]);
+    }
+    __device__ __forceinline__ static real sound(const real *nd, const Ctx<real> &c)
+    {
+        return dsqrt(c.gamma * nd[P] / nd[0]);
     }
 
     __device__ __forceinline__ static void pair(int d, const real *a, const real *b, real *f, const Ctx<real> &c)
