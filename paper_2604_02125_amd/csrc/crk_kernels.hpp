@@ -265,7 +265,16 @@ struct LocalShape {
     // Euler, whole elements per wavefront: one slot for the sound speed of
     // u^n, shared by the subcell fluxes of the blending limiter
     static constexpr int CS = (EQ == EQ_EULER && 64 % NP == 0) ? 1 : 0;
-    static constexpr int slots = Phys::NF + NX + ASL + DIM + CS;
+    // 2D, N+1 even: the pairs of the self-mirrored rotation (p, p + (N+1)/2)
+    // along x and along y are as many as the nodes.  With the Ranocha flux
+    // each lane evaluates one of them (the x pair when exactly one of its
+    // indices is below (N+1)/2, else the y pair) and takes the other from
+    // the lane that evaluated it (M slots), so that every unordered pair of
+    // the element is evaluated once.  (For the cheap KG flux the selects and
+    // the exchange cost as much as the pair.)
+    static constexpr bool BAL = DIM == 2 && SYM && KSELF > 0 && EQ == EQ_EULER && FLUX == VOL_RANOCHA;
+    static constexpr int XB = BAL ? Phys::M : 0;
+    static constexpr int slots = Phys::NF + NX + ASL + DIM + CS + XB;
 };
 
 // One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
@@ -288,7 +297,9 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     real *alds = xch + Shape::NX * BLK;   // [EPB][2 DIM + 1]
     real *llds = alds + Shape::ASL * BLK; // [DIM][BLK]
     real *clds = llds + DIM * BLK;        // [CS][BLK]
+    real *xb = clds + Shape::CS * BLK;    // [XB][BLK]
     constexpr bool CSH = Shape::CS > 0;
+    constexpr bool BAL = Shape::BAL;
     constexpr int NA = 2 * DIM + 1;
 
     const int tid = lane >= 0 ? lane : (int)threadIdx.x;   // (lane: see the batched local phase)
@@ -520,7 +531,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
             // directly evaluated rotations
 #pragma unroll
             for (int k = 1; k <= N; ++k) {
-                const bool direct = !SYM || k <= NPRIM || k == KSELF;
+                const bool direct = !SYM || k <= NPRIM || (k == KSELF && !BAL);
                 if (!direct) continue;
                 int qd = pd[d] + k;
                 if (qd >= n1) qd -= n1;
@@ -618,8 +629,34 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                 for (int v = 0; v < M; ++v) W[v] += alpha * invw[d] * (fr[v] - fl[v]);
             }
         }
+        // balanced self-mirrored rotation: the pair of direction dm
+        bool xm = false;
+        int qx = 0, qy = 0;
+        if constexpr (BAL) {
+            xm = (pd[0] < KSELF) != (pd[1] < KSELF);
+            qx = pd[0] + KSELF < n1 ? pd[0] + KSELF : pd[0] + KSELF - n1;
+            qy = pd[1] + KSELF < n1 ? pd[1] + KSELF : pd[1] + KSELF - n1;
+            const int q = xm ? line_node<N, DIM>(pd, 0, qx) : line_node<N, DIM>(pd, 1, qy);
+            real ndq[NF], fs[M];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) ndq[f] = lds[f * BLK + base + q];
+            Phys::pair_rt(xm ? 0 : 1, nd, ndq, fs, ctx);
+            const real c = xm ? Dk[0][KSELF - 1] : Dk[DIM - 1][KSELF - 1];
+#pragma unroll
+            for (int v = 0; v < M; ++v) {
+                R[v] += c * fs[v];
+                xb[v * BLK + tid] = fs[v];
+            }
+        }
         if constexpr (SYM) {
             element_sync<NP>();
+            if constexpr (BAL) {
+                // the pair of the other direction, from the lane that evaluated it
+                const int src = base + (xm ? line_node<N, DIM>(pd, 1, qy) : line_node<N, DIM>(pd, 0, qx));
+                const real c = xm ? Dk[DIM - 1][KSELF - 1] : Dk[0][KSELF - 1];
+#pragma unroll
+                for (int v = 0; v < M; ++v) R[v] += c * xb[v * BLK + src];
+            }
 #pragma unroll
             for (int d = 0; d < DIM; ++d)
 #pragma unroll

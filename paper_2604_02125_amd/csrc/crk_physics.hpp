@@ -256,6 +256,34 @@ struct EulerP {
             f[DIM + 1] = m * (ibeta_ln * c.inv_gm1 + real(0.5) * vv) + real(0.5) * (a[P] * b[1 + d] + b[P] * a[1 + d]);
         }
     }
+
+    // The Ranocha flux of pair() with a direction that varies from lane to
+    // lane: the direction enters through selects, not through the index of
+    // a field, so that no register array is indexed at run time.
+    __device__ __forceinline__ static void pair_rt(int d, const real *a, const real *b, real *f, const Ctx<real> &c)
+    {
+        static_assert(FLUX == VOL_RANOCHA, "run-time direction: Ranocha flux only");
+        real rho_ln, ibeta_ln;
+        lnmean_pair(a[0], b[0], a[DIM + 2], b[DIM + 2], a[DIM + 3], b[DIM + 3], a[DIM + 4], b[DIM + 4], rho_ln,
+                    ibeta_ln);
+        real vk[DIM], vd = real(0), avd = real(0), bvd = real(0), vv = real(0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            vk[k] = real(0.5) * (a[1 + k] + b[1 + k]);
+            vv += a[1 + k] * b[1 + k];
+            if (k == d) {
+                vd = vk[k];
+                avd = a[1 + k];
+                bvd = b[1 + k];
+            }
+        }
+        const real m = rho_ln * vd;
+        const real pm = real(0.5) * (a[P] + b[P]);
+        f[0] = m;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) f[1 + k] = m * vk[k] + (k == d ? pm : real(0));
+        f[DIM + 1] = m * (ibeta_ln * c.inv_gm1 + real(0.5) * vv) + real(0.5) * (a[P] * bvd + b[P] * avd);
+    }
 };
 
 // ---------------------------------------------------------------- GLM-MHD
