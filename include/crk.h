@@ -59,6 +59,11 @@ typedef enum {
 } crk_volume_flux;
 typedef enum { CRK_FP64 = 0, CRK_FP32 = 1 } crk_precision;
 typedef enum { CRK_LIM_NONE = 0, CRK_LIM_BLEND = 1 } crk_limiter;
+/* numerical flux at element faces of the semi-discrete operator crk_fr_rhs */
+typedef enum {
+    CRK_SURF_RUSANOV = 0,  /* eq:numflux.cons with lambda from both traces     */
+    CRK_SURF_EC = 1        /* the volume flux f_S on the two traces            */
+} crk_surface_flux;
 
 /* Uniform Cartesian periodic mesh of nx (x ny) elements on [x0,x1] (x [y0,y1]). */
 typedef struct {
@@ -134,6 +139,22 @@ crk_status crk_compute_dt(crk_solver *s, const void *u, double *dt_dev, crk_stre
  * alpha_raw[e], and alpha[e] = max(alpha_raw[e], max over face neighbours
  * of alpha_raw/2).  Device arrays of nelem doubles; either may be NULL. */
 crk_status crk_indicator(crk_solver *s, const void *u, double *alpha_raw, double *alpha, crk_stream stream);
+
+/* Test operator: the semi-discrete FR right-hand side rhs = du/dt of
+ * eq:general.non.conservative.fr.one, with the flux-differencing volume term
+ * of Section 3 (the solver's volume flux, plus B_d(u_p) g_d(u_q) for MHD) and
+ * the g2 surface correction (Huynh's g2 on GLL points: only the end nodes of
+ * a line, with weight 1/(w dx)) of the numerical flux of
+ * eq:combined.num.flux.fr: surface = CRK_SURF_RUSANOV, or CRK_SURF_EC, the
+ * volume flux on the two traces (with an entropy-conservative volume flux,
+ * zero semi-discrete entropy rate on the periodic mesh); MHD adds
+ * 1/2 B_d(u)(g_d(u^-) + g_d(u^+)) - B_d(u) g_d(u).  u and rhs: device state
+ * arrays (layout of crk_state_layout), distinct, 256-byte aligned.  dt_dev:
+ * device [dt, c_h]; only c_h is read, and only for MHD (may be NULL for
+ * Euler).  No workspace; stream-ordered; CRK_ERR_ARG on a null, misaligned
+ * or aliased pointer or an unknown surface flux. */
+crk_status crk_fr_rhs(crk_solver *s, const void *u, const double *dt_dev, int surface, void *rhs,
+                      crk_stream stream);
 
 /* Local phase (eq:crkfr.inner, eq:disc.avg.flux, Section 3 volume terms):
  * for every element the s inner stages with flux differencing, then

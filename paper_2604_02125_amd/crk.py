@@ -20,6 +20,7 @@ CRK_EULER, CRK_GLM_MHD = 0, 1
 VOL_CENTRAL, VOL_KG, VOL_RANOCHA, VOL_DERIGS = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 LIM_NONE, LIM_BLEND = 0, 1
+SURF_RUSANOV, SURF_EC = 0, 1
 STEP_COMPUTE_DT = 1
 PHASE_LOCAL, PHASE_INTERFACE = 1, 2
 
@@ -71,6 +72,7 @@ def lib():
             "crk_reference_element": (st, [C.c_int, _dp, _dp, _dp]),
             "crk_compute_dt": (st, [_vp, _vp, _vp, _vp]),
             "crk_indicator": (st, [_vp, _vp, _vp, _vp, _vp]),
+            "crk_fr_rhs": (st, [_vp, _vp, _vp, C.c_int, _vp, _vp]),
             "crk_local_stages": (st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "crk_interface_update": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
             "crk_run": (st, [_vp, _vp, _vp, _vp, C.c_int, _vp]),
@@ -194,6 +196,14 @@ class Solver:
         a = torch.empty_like(araw)
         _check(lib().crk_indicator(self._h, _ptr(u), _ptr(araw), _ptr(a), _stream(stream)), "crk_indicator")
         return araw, a
+
+    def fr_rhs(self, u, surface=SURF_RUSANOV, dt=None, stream=None):
+        """Semi-discrete FR right-hand side du/dt (test operator); dt = [dt, c_h] on the device (MHD)."""
+        self._check_state(u)
+        out = self.new_state()
+        _check(lib().crk_fr_rhs(self._h, _ptr(u), _ptr(dt), int(surface), _ptr(out), _stream(stream)),
+               "crk_fr_rhs")
+        return out
 
     def local_stages(self, u_in, dt, u_out, traces, alpha=None, stream=None):
         self._check_state(u_in)

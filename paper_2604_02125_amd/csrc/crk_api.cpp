@@ -365,6 +365,20 @@ crk_status crk_compute_dt(crk_solver *s, const void *u, double *dt_dev, crk_stre
     return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_compute_dt");
 }
 
+crk_status crk_fr_rhs(crk_solver *s, const void *u, const double *dt_dev, int surface, void *rhs, crk_stream stream)
+{
+    if (!s || !u || !rhs) return fail(CRK_ERR_ARG, "null argument");
+    if (!is_aligned(u) || !is_aligned(rhs)) return fail(CRK_ERR_ARG, "device arrays must be 256-byte aligned");
+    if (u == rhs) return fail(CRK_ERR_ARG, "u and rhs must not alias");
+    if (surface != CRK_SURF_RUSANOV && surface != CRK_SURF_EC) return fail(CRK_ERR_ARG, "unknown surface flux");
+    if (s->mesh.equation == CRK_GLM_MHD && !dt_dev) return fail(CRK_ERR_ARG, "MHD needs c_h in dt_dev[1]");
+    hipError_t e = dispatch(s, [&](auto fam) {
+        return decltype(fam)::fr_rhs(s->t, s->flux, u, s->mesh.equation == CRK_GLM_MHD ? dt_dev : nullptr, surface,
+                                     rhs, (hipStream_t)stream);
+    });
+    return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_fr_rhs");
+}
+
 crk_status crk_indicator(crk_solver *s, const void *u, double *alpha_raw, double *alpha, crk_stream stream)
 {
     if (!s || !u) return fail(CRK_ERR_ARG, "null argument");

@@ -18,6 +18,9 @@ struct Family {
     static hipError_t indicator(const Tables &t, const void *u, double *araw, double *alpha, float *features, hipStream_t s);
     static hipError_t dt(const Tables &t, const void *u, double *partials, double *dt, hipStream_t s);
     static hipError_t diag(const Tables &t, const void *u, double *partials, double *out, hipStream_t s);
+    // semi-discrete FR operator du/dt of u into rhs (test operator, crk_rhs.hpp)
+    static hipError_t fr_rhs(const Tables &t, int flux, const void *u, const double *dtc, int surface, void *rhs,
+                             hipStream_t s);
 };
 
 // fluxes compiled for an equation system

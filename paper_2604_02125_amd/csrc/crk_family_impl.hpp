@@ -2,6 +2,7 @@
 // per family translation unit, followed by an explicit instantiation.
 #pragma once
 #include "crk_dispatch.hpp"
+#include "crk_rhs.hpp"
 
 namespace crk {
 
@@ -34,6 +35,29 @@ template <typename real, int EQ, int DIM>
 hipError_t Family<real, EQ, DIM>::interface(const Tables &t, int flux, const StepPtrs &p, hipStream_t s)
 {
     CRK_DEGREE_SWITCH(launch_interface)
+}
+
+template <typename real, int EQ, int DIM>
+hipError_t Family<real, EQ, DIM>::fr_rhs(const Tables &t, int flux, const void *u, const double *dtc, int surface,
+                                         void *rhs, hipStream_t s)
+{
+#define CRK_RHS_FLUX(NN)                                                                                        \
+    switch (flux) {                                                                                             \
+    case VOL_CENTRAL: return launch_fr_rhs<real, EQ, DIM, NN, VOL_CENTRAL>(t, u, dtc, surface, rhs, s);        \
+    case VOL_KG: if constexpr (EQ == EQ_EULER) return launch_fr_rhs<real, EQ, DIM, NN, VOL_KG>(t, u, dtc, surface, rhs, s); break;           \
+    case VOL_RANOCHA: if constexpr (EQ == EQ_EULER) return launch_fr_rhs<real, EQ, DIM, NN, VOL_RANOCHA>(t, u, dtc, surface, rhs, s); break; \
+    case VOL_DERIGS: if constexpr (EQ == EQ_MHD) return launch_fr_rhs<real, EQ, DIM, NN, VOL_DERIGS>(t, u, dtc, surface, rhs, s); break;     \
+    default: break;                                                                                             \
+    }                                                                                                           \
+    return hipErrorInvalidValue;
+    switch (t.N) {
+    case 1: { CRK_RHS_FLUX(1) }
+    case 2: { CRK_RHS_FLUX(2) }
+    case 3: { CRK_RHS_FLUX(3) }
+    case 4: { CRK_RHS_FLUX(4) }
+    default: return hipErrorInvalidValue;
+    }
+#undef CRK_RHS_FLUX
 }
 
 template <typename real, int EQ, int DIM>

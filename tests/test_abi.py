@@ -98,3 +98,23 @@ def test_calls_without_workspace_fail_cleanly():
     assert crk.lib().crk_run(h, C.c_void_p(256), C.c_void_p(4096), C.c_void_p(768), 5, None) == -6
     assert crk.lib().crk_advance(h, C.c_void_p(256), C.c_void_p(4096), C.c_void_p(768), 4, None) == -1
     crk.lib().crk_destroy(h)
+
+
+def test_fr_rhs_validation():
+    # the semi-discrete test operator validates its arguments before any launch
+    L = crk.lib()
+    for eq, vol in ((crk.CRK_EULER, crk.VOL_KG), (crk.CRK_GLM_MHD, crk.VOL_DERIGS)):
+        m = crk.MeshDesc(2, 4, 4, 0.0, 1.0, 0.0, 1.0, 3, eq, 1.4, crk.FP64)
+        sc = crk.SchemeDesc()
+        sc.volume_flux, sc.cfl = vol, 0.4
+        h = C.c_void_p()
+        assert L.crk_create(C.byref(m), C.byref(sc), C.byref(h)) == 0
+        u, r, dt = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20)
+        assert L.crk_fr_rhs(h, u, dt, 7, r, None) == -1                    # unknown surface flux
+        assert L.crk_fr_rhs(h, u, dt, crk.SURF_EC, u, None) == -1          # aliasing
+        assert L.crk_fr_rhs(h, C.c_void_p((1 << 20) + 8), dt, 0, r, None) == -1   # misaligned
+        assert L.crk_fr_rhs(h, None, dt, 0, r, None) == -1
+        if eq == crk.CRK_GLM_MHD:
+            assert L.crk_fr_rhs(h, u, None, 0, r, None) == -1              # MHD needs c_h
+            assert "c_h" in L.crk_last_error().decode()
+        L.crk_destroy(h)
