@@ -124,7 +124,10 @@ struct crk_solver {
     Tables t;
     size_t elem_bytes;
     size_t state_bytes, trace_bytes;
-    size_t off_partials, off_slots, off_araw, off_alpha, off_features, off_traces, ws_bytes;
+    size_t off_partials, off_slots, off_araw, off_alpha, off_features, off_tiles, off_traces, ws_bytes;
+    long ntiles;     // local-phase tiles (two flag sets of ntiles ints in the workspace)
+    int tparity;     // flag set of the next local phase
+    bool tiles_valid; // the flag set covers the raw coefficients in the workspace
     const uint16_t *mlp;          // learned indicator parameters (BF16, device) or nullptr
     const float *mlp_lo, *mlp_hi; // feature range the network was trained on
     char *ws;
@@ -132,6 +135,18 @@ struct crk_solver {
 };
 
 namespace {
+
+// Tile flags (pipelined step with the modal indicator, 2D, Kennedy-Gruber
+// flux): flagged-clear tiles take the local-phase instance without the
+// blending code, whose register count allows a fourth wavefront per SIMD in
+// FP64 (120 instead of 156 VGPRs) and a seventh in FP32; with the Ranocha
+// flux it stays at three in FP64 and the second launch would cost more than
+// it saves.  A 1D mesh small enough for crk_run's single launch keeps the
+// blending instance so that both give the same bits.
+bool use_tile_flags(const crk_solver *s)
+{
+    return s->limiter == CRK_LIM_BLEND && !s->mlp && s->mesh.dim == 2 && s->flux == CRK_VOL_KG;
+}
 
 template <class F>
 hipError_t dispatch(const crk_solver *s, F &&f)
@@ -305,10 +320,14 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     s->off_araw = off; off = align256(off + sizeof(double) * nelem);
     s->off_alpha = off; off = align256(off + sizeof(double) * nelem);
     s->off_features = off; off = align256(off + sizeof(float) * nelem * nnode);
+    s->ntiles = elem_blocks;
+    s->off_tiles = off; off = align256(off + sizeof(int) * 2 * elem_blocks);
     s->off_traces = off; off = align256(off + s->trace_bytes);
     s->ws_bytes = off;
     s->ws = nullptr;
     s->prepared = false;
+    s->tparity = 0;
+    s->tiles_valid = false;
     s->mlp = nullptr;
     s->mlp_lo = s->mlp_hi = nullptr;
     *out = s;
@@ -388,7 +407,10 @@ crk_status crk_indicator(crk_solver *s, const void *u, double *alpha_raw, double
         crk_status st = need_ws(s);
         if (st) return st;
     }
-    if (!araw) araw = (double *)(s->ws + s->off_araw);
+    if (!araw) {
+        araw = (double *)(s->ws + s->off_araw);
+        s->tiles_valid = false;   // the tile flags no longer describe these coefficients
+    }
     float *feat = s->mlp ? (float *)(s->ws + s->off_features) : nullptr;
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::indicator(s->t, u, araw, nullptr, feat, hs); });
@@ -511,6 +533,22 @@ crk_status crk_prepare(crk_solver *s, const void *u, double *dt_dev, crk_stream 
     // the wave-speed slots the interface phases merge into start at zero
     // (a fill kernel, not a memset: safe inside a captured graph)
     if (e == hipSuccess) e = launch_zero((double *)(s->ws + s->off_slots), DT_SLOTS, (hipStream_t)stream);
+    // tile flags of u (pipelined limiter with the modal indicator): both sets
+    // cleared, set 0 marked from the raw coefficients
+    s->tparity = 0;
+    s->tiles_valid = false;
+    if (e == hipSuccess && use_tile_flags(s)) {
+        int *tiles = (int *)(s->ws + s->off_tiles);
+        e = launch_zero_int(tiles, (int)(2 * s->ntiles), (hipStream_t)stream);
+        if (e == hipSuccess) {
+            const long epb = tile_block_rt((int)s->t.nnode) / s->t.nnode;
+            const dim3 g((unsigned)((s->t.nelem + BLOCK - 1) / BLOCK));
+            const double *araw = (const double *)(s->ws + s->off_araw);
+            hipLaunchKernelGGL(k_mark_tiles<2>, g, dim3(BLOCK), 0, (hipStream_t)stream, s->t, araw, (int)epb, tiles);
+            e = hipGetLastError();
+        }
+        s->tiles_valid = e == hipSuccess;
+    }
     if (e != hipSuccess) return hip_fail(e, "crk_prepare");
     s->prepared = true;
     return CRK_OK;
@@ -529,12 +567,20 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
     double *araw = (double *)(s->ws + s->off_araw);
     double *alpha = (double *)(s->ws + s->off_alpha);
     void *tr = s->ws + s->off_traces;
+    // tile flags: set tparity is this step's, the other one the next step's
+    const bool flags = use_tile_flags(s);
+    int *tiles = (int *)(s->ws + s->off_tiles);
+    int *t_cur = tiles + (size_t)s->tparity * s->ntiles, *t_next = tiles + (size_t)(1 - s->tparity) * s->ntiles;
     hipError_t e = hipSuccess;
     if (phases & CRK_PHASE_LOCAL) {
         StepPtrs p{};
         p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = tr;
         p.alpha_raw = lim ? araw : nullptr;
         p.alpha_s = alpha;
+        if (flags && s->tiles_valid) {
+            p.tiles_in = t_cur;
+            p.tiles_out = t_next;
+        }
         e = dispatch(s, [&](auto fam) { return decltype(fam)::local(s->t, s->flux, p, (hipStream_t)stream); });
         if (e != hipSuccess) return hip_fail(e, "crk_advance (local phase)");
     }
@@ -545,6 +591,10 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
         p.partials = (double *)(s->ws + s->off_slots);
         p.dt_out = dt_dev;
         p.features = (lim && s->mlp) ? (float *)(s->ws + s->off_features) : nullptr;
+        // marks only add to the next step's set: a set that the local phase
+        // did not clear is a superset, which is safe (flagged tiles blend
+        // with whatever coefficients they find)
+        if (flags) p.tiles_out = t_next;
         e = dispatch(s, [&](auto fam) { return decltype(fam)::interface(s->t, s->flux, p, (hipStream_t)stream); });
         if (e == hipSuccess && p.features)
             e = launch_mlp_alpha(s->mlp, p.features, s->mlp_lo, s->mlp_hi, s->t.nelem, s->t.alpha_max,
@@ -552,6 +602,10 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
         if (e != hipSuccess) {
             s->prepared = false;   // the slots may not be back at zero
             return hip_fail(e, "crk_advance (interface phase)");
+        }
+        if (flags) {
+            s->tparity ^= 1;
+            s->tiles_valid = true;
         }
     }
     return CRK_OK;
@@ -577,7 +631,10 @@ crk_status crk_run(crk_solver *s, void *u0, void *u1, double *dt_dev, int nsteps
         p.partials = (double *)(s->ws + s->off_partials);
         hipError_t e = dispatch(s, [&](auto fam) {
             return decltype(fam)::run(s->t, s->flux, p, dt_dev, nsteps, (hipStream_t)stream); });
-        if (e == hipSuccess) return CRK_OK;
+        if (e == hipSuccess) {
+            s->tiles_valid = false;   // the fused steps keep no tile flags
+            return CRK_OK;
+        }
         if (e != hipErrorNotSupported) return hip_fail(e, "crk_run");
     }
     for (int k = 0; k < nsteps; ++k) {

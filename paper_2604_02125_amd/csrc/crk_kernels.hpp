@@ -96,6 +96,13 @@ struct StepPtrs {
     double *partials;         // interface phase: wave-speed maxima (k_interface: DT_SLOTS slots, zero on entry)
     double *dt_out;           // interface phase: dt and c_h of u_out (finished by k_dt_slots), or nullptr
     float *features;          // interface phase: learned-indicator features of u_out, or nullptr
+    // Pipelined step with the limiter: one flag per local-phase tile, set when
+    // a raw coefficient within two faces of one of its elements is positive
+    // (only such tiles can blend).  Local phase: tiles_in are the step's
+    // flags, tiles_out (the next step's) are cleared; interface phase: the
+    // flags of u_out are marked into tiles_out.  nullptr: no flags.
+    const int *tiles_in;
+    int *tiles_out;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -279,7 +286,10 @@ struct LocalShape {
 
 // One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
 // smem holds LocalShape::slots * BLK values.
-template <typename real, int EQ, int DIM, int N, int FLUX, int S, int BLK, int TAB = 0>
+// BLEND = false: no blending coefficient can be positive in the tile (no
+// limiter, or a flagged-clear tile of the pipelined step); the blending code
+// is compiled out, which frees registers for a fourth wavefront per SIMD.
+template <typename real, int EQ, int DIM, int N, int FLUX, int S, int BLK, int TAB = 0, bool BLEND = true>
 __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, long e0, real *smem, int lane = -1)
 {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
@@ -386,9 +396,13 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     // element: given (alpha), or in the pipelined step alpha_e =
     // max(alpha_raw_e, max over face neighbours of alpha_raw / 2); read after
     // the first stage's barrier
-    const bool smooth = a.alpha_raw != nullptr;
-    const bool blend = smooth || a.alpha != nullptr;
+    const bool smooth = BLEND && a.alpha_raw != nullptr;
+    const bool blend = BLEND && (smooth || a.alpha != nullptr);
     real alpha = real(0);
+    if constexpr (!BLEND) {
+        // pipelined step: the smoothed coefficient of a clear tile is zero
+        if (a.alpha_raw != nullptr && valid && node == 0) a.alpha_s[e] = 0.0;
+    }
     if (blend && valid) {
 #pragma unroll
         for (int r = 0; r < (NA + NP - 1) / NP; ++r) {
@@ -725,13 +739,25 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     for (int v = 0; v < M; ++v) uout[((long)v * E + e) * NP + node] = un[v] - rdt * W[v];
 }
 
-template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB = 0>
+// With tile flags, the BLEND = false instance runs the clear tiles (and
+// clears every tile's flag of the next step) and the BLEND = true instance,
+// launched after it, the flagged ones; a workgroup leaves at once on a tile
+// of the other kind.
+template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB = 0, bool BLEND = true>
 __global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 1>()) k_local(const Tables t, const StepPtrs a)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     constexpr int TB = tile_block<NP>();
     __shared__ real smem[LocalShape<real, EQ, DIM, N, FLUX>::slots * TB];
-    local_tile<real, EQ, DIM, N, FLUX, S, TB, TAB>(t, a, xcd_tile(blockIdx.x, gridDim.x) * (TB / NP), smem);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (a.tiles_in != nullptr) {
+        const int flagged = a.tiles_in[tile];
+        if constexpr (!BLEND) {
+            if (threadIdx.x == 0) a.tiles_out[tile] = 0;
+        }
+        if (BLEND ? flagged == 0 : flagged != 0) return;
+    }
+    local_tile<real, EQ, DIM, N, FLUX, S, TB, TAB, BLEND>(t, a, (long)tile * (TB / NP), smem);
 }
 
 // ---------------------------------------------------------------- K8 helper: modal indicator
@@ -749,10 +775,32 @@ __device__ __forceinline__ double group_sum(double x)
     return x;
 }
 
+// Flag the local-phase tiles (epb elements each) of element e, of its face
+// neighbours and of theirs: every tile whose blending coefficients can
+// depend on alpha_raw[e] (smoothing over faces, face factor of neighbours).
+template <int DIM>
+__device__ __forceinline__ void mark_tiles(const Tables &t, long e, int epb, int *tiles)
+{
+    tiles[e / epb] = 1;
+    const Nbrs nb = neighbours<DIM>(t, e);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            const long n = nb.n[d][sd];
+            tiles[n / epb] = 1;
+            const Nbrs n2 = neighbours<DIM>(t, n);
+#pragma unroll
+            for (int d2 = 0; d2 < DIM; ++d2)
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) tiles[n2.n[d2][s2] / epb] = 1;
+        }
+}
+
 template <int DIM, int N, int BLK>
 __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le, int node, long e, bool valid,
                                                 double eps_node, double *eps, double *en, double *alpha_raw,
-                                                float *features)
+                                                float *features, int *tiles = nullptr)
 {
     constexpr int n1 = N + 1;
     constexpr int NP = DIM == 2 ? n1 * n1 : n1;
@@ -803,14 +851,37 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
             }
         }
     }
-    if (valid && node == 0) {
+    if (valid) {
+        // every lane of the element forms the same coefficient
         const double E1 = (tot - c1) / tot, E2 = (c1 - c2) / c1;
         const double En = E1 > E2 ? E1 : E2;
         double al = 1.0 / (1.0 + exp(-(t.ind_sharpness / t.ind_threshold) * (En - t.ind_threshold)));
         if (al < t.alpha_min) al = 0.0;
         if (al > 1.0 - t.alpha_min) al = 1.0;
         if (al > t.alpha_max) al = t.alpha_max;
-        alpha_raw[e] = al;
+        if (node == 0) alpha_raw[e] = al;
+        // tile flags (2D): lane j < 13 of a blending element flags the tile
+        // of the j-th element within two faces of it (the element, its four
+        // face neighbours, the four at distance two along x or y and the
+        // four diagonal ones), periodic
+        if constexpr (DIM == 2) {
+            if (tiles != nullptr && al > 0.0 && node < 13) {
+                const int r = node < 9 ? (node - 1) & 3 : node - 9;
+                int dx = 0, dy = 0;
+                if (node >= 1 && node <= 8) {
+                    const int s = node <= 4 ? 1 : 2;
+                    dx = r == 0 ? s : (r == 1 ? -s : 0);
+                    dy = r == 2 ? s : (r == 3 ? -s : 0);
+                } else if (node >= 9) {
+                    dx = (r & 1) ? 1 : -1;
+                    dy = (r & 2) ? 1 : -1;
+                }
+                const int nx = t.nx, ny = t.ny, ei = (int)e;
+                const int ey = ei / nx, ex = ei - ey * nx;
+                const int x = ((ex + dx) % nx + nx) % nx, y = ((ey + dy) % ny + ny) % ny;
+                tiles[(y * nx + x) / (BLK / NP)] = 1;
+            }
+        }
     }
     // features of the learned indicator: the modal energy fractions
     // f = m_kl^2 / sum m^2 on a log scale, 1 + log10(max(f, 1e-16))/16 in [0, 1]
@@ -977,7 +1048,7 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
             real rho, v[DIM], p, Ev;
             Phys::prim(nd, rho, v, p, Ev, ctx);
             indicator_lanes<DIM, N, BLK>(t, tid, le, node, e, valid, (double)rho * (double)p, dsmem + BLK,
-                                         dsmem + 2 * BLK, a.alpha_raw_out, a.features);
+                                         dsmem + 2 * BLK, a.alpha_raw_out, a.features, a.tiles_out);
         }
     }
     if constexpr (SLOTS) block_max_lanes<BLK, true>(sp, dsmem, a.partials + slot % DT_SLOTS);
@@ -1018,7 +1089,7 @@ __device__ __forceinline__ void finish_dt(const Tables &t, double m, int is_mhd,
 // LDS between the steps.  Same device code and arithmetic as the separate
 // launches.
 constexpr int RUN_BLOCK = 256;   // one wavefront per SIMD: no register cap
-template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB>
+template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB, bool BLEND>
 __global__ void __launch_bounds__(RUN_BLOCK) k_run(const Tables t, const StepPtrs a0, double *dt_io, int nsteps)
 {
     constexpr size_t LB = (size_t)LocalShape<real, EQ, DIM, N, FLUX>::slots * RUN_BLOCK * sizeof(real);
@@ -1035,7 +1106,7 @@ __global__ void __launch_bounds__(RUN_BLOCK) k_run(const Tables t, const StepPtr
     __syncthreads();
     for (int k = 0; k < nsteps; ++k) {
         const StepPtrs &p = (k & 1) ? ao : ae;
-        local_tile<real, EQ, DIM, N, FLUX, S, RUN_BLOCK, TAB>(t, p, 0, (real *)pool);
+        local_tile<real, EQ, DIM, N, FLUX, S, RUN_BLOCK, TAB, BLEND>(t, p, 0, (real *)pool);
         __syncthreads();
         interface_tile<real, EQ, DIM, N, FLUX, RUN_BLOCK>(t, p, 0, 0, pool);
         __syncthreads();
@@ -1135,6 +1206,19 @@ static __global__ void k_zero(double *p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;
+}
+
+// tile flags of a state from its raw coefficients (flags zero on entry)
+template <int DIM>
+__global__ void __launch_bounds__(BLOCK) k_mark_tiles(const Tables t, const double *alpha_raw, int epb, int *tiles)
+{
+    const long e = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (e < t.nelem && alpha_raw[e] > 0.0) mark_tiles<DIM>(t, e, epb, tiles);
+}
+static __global__ void k_zero_int(int *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // ---------------------------------------------------------------- K8: modal indicator
@@ -1266,21 +1350,43 @@ hipError_t launch_local(const Tables &t, const StepPtrs &p, hipStream_t s)
     constexpr int TB = tile_block<NP>();
     constexpr int EPB = TB / NP;
     const int grid = (t.nelem + EPB - 1) / EPB;
-    switch (t.stages) {
-    case 1: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 1>), dim3(grid), dim3(TB), 0, s, t, p); break;
-    case 2: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 2>), dim3(grid), dim3(TB), 0, s, t, p); break;
-    case 3: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 3>), dim3(grid), dim3(TB), 0, s, t, p); break;
-    case 4:
-        if (t.tableau == 1) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 1>), dim3(grid), dim3(TB), 0, s, t, p);
-        else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4>), dim3(grid), dim3(TB), 0, s, t, p);
-        break;
-    case 5: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 5>), dim3(grid), dim3(TB), 0, s, t, p); break;
-    case 6:
-        if (t.tableau == 2) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6, 2>), dim3(grid), dim3(TB), 0, s, t, p);
-        else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6>), dim3(grid), dim3(TB), 0, s, t, p);
-        break;
-    default: return hipErrorInvalidValue;
+#define CRK_LOCAL_LAUNCH(BL)                                                                                       \
+    switch (t.stages) {                                                                                            \
+    case 1: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 1, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p); break; \
+    case 2: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 2, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p); break; \
+    case 3: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 3, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p); break; \
+    case 4:                                                                                                        \
+        if (t.tableau == 1) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 1, BL>), dim3(grid), dim3(TB), 0, s, t, p); \
+        else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p);  \
+        break;                                                                                                     \
+    case 5: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 5, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p); break; \
+    case 6:                                                                                                        \
+        if (t.tableau == 2) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6, 2, BL>), dim3(grid), dim3(TB), 0, s, t, p); \
+        else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p);  \
+        break;                                                                                                     \
+    default: return hipErrorInvalidValue;                                                                          \
     }
+    // without blending coefficients (no limiter) every tile takes the
+    // instance without the blending code; with tile flags both run, the
+    // blending one second; with given coefficients only the blending one
+    const bool blend = p.alpha != nullptr || p.alpha_raw != nullptr;
+    if (!blend || p.tiles_in != nullptr) {
+        CRK_LOCAL_LAUNCH(false)
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if constexpr (EQ == EQ_EULER) {
+        if (blend) {
+            CRK_LOCAL_LAUNCH(true)
+        }
+    }
+#undef CRK_LOCAL_LAUNCH
+    return hipGetLastError();
+}
+
+inline hipError_t launch_zero_int(int *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_int, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, p, n);
     return hipGetLastError();
 }
 
@@ -1302,7 +1408,13 @@ hipError_t launch_run(const Tables &t, const StepPtrs &p, double *dt, int nsteps
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     if ((long)t.nelem * NP > RUN_BLOCK) return hipErrorInvalidValue;
-#define CRK_RUN(SS, TT) hipLaunchKernelGGL((k_run<real, EQ, DIM, N, FLUX, SS, TT>), dim3(1), dim3(RUN_BLOCK), 0, s, t, p, dt, nsteps)
+    // the instance the separate local-phase launches use (no tile flags here)
+    const bool blend = p.alpha_raw != nullptr;
+#define CRK_RUN(SS, TT)                                                                                              \
+    do {                                                                                                             \
+        if (blend) hipLaunchKernelGGL((k_run<real, EQ, DIM, N, FLUX, SS, TT, true>), dim3(1), dim3(RUN_BLOCK), 0, s, t, p, dt, nsteps); \
+        else hipLaunchKernelGGL((k_run<real, EQ, DIM, N, FLUX, SS, TT, false>), dim3(1), dim3(RUN_BLOCK), 0, s, t, p, dt, nsteps); \
+    } while (0)
     switch (t.stages) {
     case 1: CRK_RUN(1, 0); break;
     case 2: CRK_RUN(2, 0); break;

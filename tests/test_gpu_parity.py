@@ -483,7 +483,8 @@ def test_full_size_mhd_parity(orc):
     assert rel <= TOL64
 
 
-@pytest.mark.parametrize("case", ["khi_blend", "khi_blend_N2", "khi_blend_ranocha", "euler2d_N1", "euler1d", "mhd"])
+@pytest.mark.parametrize("case", ["khi_blend", "khi_blend_N2", "khi_blend_ranocha", "khi_blend_kg_N4", "euler2d_N1",
+                                  "euler1d", "mhd"])
 def test_pipelined_advance(orc, case):
     """crk_prepare + crk_advance (CFL reduction and indicator fused into the
     interface phase) against the oracle trajectory and against crk_step."""
@@ -493,6 +494,10 @@ def test_pipelined_advance(orc, case):
     elif case == "khi_blend_ranocha":
         # N=3 Ranocha: every node pair evaluated once (per-lane direction), with the subcell branch
         p, s = _pair(orc, dim=2, nx=21, ny=26, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=2,
+                     limiter=orc.LIM_BLEND_MODAL)
+    elif case == "khi_blend_kg_N4":
+        # tile flags with 256-lane workgroups of ten elements, ragged last tile
+        p, s = _pair(orc, dim=2, nx=17, ny=13, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=4, vol_flux=1,
                      limiter=orc.LIM_BLEND_MODAL)
     elif case == "khi_blend_N2":
         p, s = _pair(orc, dim=2, nx=27, ny=22, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=2, vol_flux=2,
