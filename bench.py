@@ -31,16 +31,18 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 
-# Per launch of k_local on the KHI 256^2 FP64 workload, from rocprofv3 --pmc:
+# Per local phase of the KHI 256^2 FP64 workload (with the Kennedy-Gruber flux
+# both k_local instances, the one for flagged tiles and the one for the rest),
+# from rocprofv3 --pmc:
 # HBM bytes = FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB, scaled by the plain-copy
 # calibration) and FP64 FLOPs = SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes; valid only
 # for the kernel sources whose digest is recorded with them.
 MEASURED_TRAFFIC = {
-    ("khi256", "fp64"): {"sources_sha256": "21d8fcf8811bf2c5b7984f6ca60bb681b0720f8bc07673dde5763da88ea240db",
-                         "bytes": (2.0 * 20925.5 + 1.0 * 66048.0) * 1024,
-                         "fp64_flops": 15941632.0 * 64},
-    ("khi256_ranocha", "fp64"): {"sources_sha256": "21d8fcf8811bf2c5b7984f6ca60bb681b0720f8bc07673dde5763da88ea240db",
-                                 "bytes": (2.0 * 21009.1 + 1.0 * 66048.0) * 1024,
+    ("khi256", "fp64"): {"sources_sha256": "e4097fec15da402df7d32c5492e2ef2357957e9dc3a4f504d273d83aec4a3f94",
+                         "bytes": (2.0 * 20753.2 + 1.0 * 66112.0) * 1024,
+                         "fp64_flops": 15433728.0 * 64},
+    ("khi256_ranocha", "fp64"): {"sources_sha256": "e4097fec15da402df7d32c5492e2ef2357957e9dc3a4f504d273d83aec4a3f94",
+                                 "bytes": (2.0 * 21010.8 + 1.0 * 66048.0) * 1024,
                                  "fp64_flops": 38551552.0 * 64},
 }
 KERNEL_SOURCES = ("paper_2604_02125_amd/csrc/crk_kernels.hpp", "paper_2604_02125_amd/csrc/crk_physics.hpp")
