@@ -51,8 +51,9 @@ __global__ void __launch_bounds__(BLK) k_batch_local(const BatchProblem *probs, 
     auto tile = [&](int it, int lane) {
         const BatchTile tl = tiles[it];
         const BatchProblem &bp = probs[tl.prob];
-        if constexpr (NDEG == 3) local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK, 1>(bp.t, bp.p[dir], tl.e0, smem, lane);
-        else local_tile<real, EQ_EULER, 2, 4, FLUX, 6, BLK, 2>(bp.t, bp.p[dir], tl.e0, smem, lane);
+        // batches have no limiter: the instance without the blending code
+        if constexpr (NDEG == 3) local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK, 1, false>(bp.t, bp.p[dir], tl.e0, smem, lane);
+        else local_tile<real, EQ_EULER, 2, 4, FLUX, 6, BLK, 2, false>(bp.t, bp.p[dir], tl.e0, smem, lane);
     };
     if constexpr (PERSIST) {
         for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
