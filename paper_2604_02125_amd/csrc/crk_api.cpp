@@ -16,7 +16,8 @@ using namespace crk;
 
 namespace crk {
 hipError_t launch_mlp_alpha(const uint16_t *theta, const float *features, const float *lo, const float *hi, long nelem,
-                            double alpha_max, double alpha_min, double *alpha_raw, hipStream_t s);
+                            double alpha_max, double alpha_min, double *alpha_raw, const Tables *t, int *tiles,
+                            hipStream_t s);
 hipError_t launch_labels(const Tables &t, int prec, const void *un, const void *uh, double tol, float *labels,
                          hipStream_t s);
 }
@@ -136,8 +137,8 @@ struct crk_solver {
 
 namespace {
 
-// Tile flags (pipelined step with the modal indicator, 2D, Kennedy-Gruber
-// flux): flagged-clear tiles take the local-phase instance without the
+// Tile flags (pipelined step with the limiter, 2D, Kennedy-Gruber flux;
+// the learned indicator flags from its own coefficients as well): flagged-clear tiles take the local-phase instance without the
 // blending code, whose register count allows a fourth wavefront per SIMD in
 // FP64 (120 instead of 156 VGPRs) and a seventh in FP32; with the Ranocha
 // flux it stays at three in FP64 and the second launch would cost more than
@@ -145,7 +146,7 @@ namespace {
 // blending instance so that both give the same bits.
 bool use_tile_flags(const crk_solver *s)
 {
-    return s->limiter == CRK_LIM_BLEND && !s->mlp && s->mesh.dim == 2 && s->flux == CRK_VOL_KG;
+    return s->limiter == CRK_LIM_BLEND && s->mesh.dim == 2 && s->flux == CRK_VOL_KG;
 }
 
 template <class F>
@@ -415,7 +416,8 @@ crk_status crk_indicator(crk_solver *s, const void *u, double *alpha_raw, double
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::indicator(s->t, u, araw, nullptr, feat, hs); });
     if (e == hipSuccess && s->mlp)
-        e = launch_mlp_alpha(s->mlp, feat, s->mlp_lo, s->mlp_hi, s->t.nelem, s->t.alpha_max, s->t.alpha_min, araw, hs);
+        e = launch_mlp_alpha(s->mlp, feat, s->mlp_lo, s->mlp_hi, s->t.nelem, s->t.alpha_max, s->t.alpha_min, araw,
+                             nullptr, nullptr, hs);
     if (e == hipSuccess && alpha) {
         hipLaunchKernelGGL(k_smooth, dim3((s->t.nelem + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, hs, s->t,
                            (const double *)araw, alpha);
@@ -598,7 +600,7 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
         e = dispatch(s, [&](auto fam) { return decltype(fam)::interface(s->t, s->flux, p, (hipStream_t)stream); });
         if (e == hipSuccess && p.features)
             e = launch_mlp_alpha(s->mlp, p.features, s->mlp_lo, s->mlp_hi, s->t.nelem, s->t.alpha_max,
-                                 s->t.alpha_min, araw, (hipStream_t)stream);
+                                 s->t.alpha_min, araw, &s->t, p.tiles_out, (hipStream_t)stream);
         if (e != hipSuccess) {
             s->prepared = false;   // the slots may not be back at zero
             return hip_fail(e, "crk_advance (interface phase)");

@@ -259,7 +259,7 @@ static_assert(NIN == 16 && HID == 64, "the tiling below is written for 16 inputs
 
 __global__ void __launch_bounds__(256) k_mlp_alpha(const uint16_t *theta, const float *features, const float *lo,
                                                    const float *hi, long nelem, double alpha_max, double alpha_min,
-                                                   double *alpha_raw)
+                                                   double *alpha_raw, const crk::Tables t, int epb, int *tiles)
 {
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, kq = lane >> 4;
@@ -341,6 +341,8 @@ __global__ void __launch_bounds__(256) k_mlp_alpha(const uint16_t *theta, const 
             double a = alpha_max / (1.0 + exp(-(double)z));
             if (a < alpha_min) a = 0.0;
             alpha_raw[e] = a;
+            // local-phase tile flags of the pipelined step (2D meshes)
+            if (tiles != nullptr && a > 0.0) crk::mark_tiles<2>(t, e, epb, tiles);
         }
     }
 }
@@ -426,15 +428,20 @@ inline unsigned blocks(long n, int b) { return (unsigned)((n + b - 1) / b); }
 namespace crk {
 // used by crk_api.cpp: learned blending coefficients over the modal ones
 hipError_t launch_mlp_alpha(const uint16_t *theta, const float *features, const float *lo, const float *hi, long nelem,
-                            double alpha_max, double alpha_min, double *alpha_raw, hipStream_t s)
+                            double alpha_max, double alpha_min, double *alpha_raw, const Tables *t, int *flags,
+                            hipStream_t s)
 {
     // four wavefronts per workgroup, each walking tiles of 16 elements; at
     // most two wavefronts per SIMD of the 256 CUs (the register budget)
     const long tiles = (nelem + MX_TILE - 1) / MX_TILE;
     long g = (tiles + 3) / 4;
     if (g > 256 * 2) g = 256 * 2;
+    // flags: local-phase tile flags of the 2D mesh described by *t, or nullptr
+    const bool mark = flags != nullptr && t != nullptr;
+    const Tables tt = mark ? *t : Tables{};
+    const int epb = mark ? tile_block_rt((int)tt.nnode) / (int)tt.nnode : 1;
     hipLaunchKernelGGL(k_mlp_alpha, dim3((unsigned)g), dim3(256), 0, s, theta, features, lo, hi, nelem, alpha_max,
-                       alpha_min, alpha_raw);
+                       alpha_min, alpha_raw, tt, epb, mark ? flags : nullptr);
     return hipGetLastError();
 }
 hipError_t launch_labels(const Tables &t, int prec, const void *un, const void *uh, double tol, float *labels, hipStream_t s)

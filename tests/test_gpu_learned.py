@@ -178,3 +178,34 @@ def test_gain_over_modal_indicator(orc):
     print(f"sum alpha: modal {res['modal']['asum']:.3f}, learned {res['mlp']['asum']:.3f}; "
           f"alpha>0 disagreement on the final state {disagree:.4f}")
     assert res["mlp"]["asum"] < res["modal"]["asum"]
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_pipelined_learned_tile_flags(orc):
+    """Pipelined steps with the trained network bound, where the network's
+    own coefficients flag the local-phase tiles that may blend, against
+    crk_step with the same network, which runs the blending code on every
+    tile.  A tile left unflagged would skip its blending (an O(alpha)
+    difference)."""
+    p, s, u = _khi_pair(orc, n=32)
+    crk.MLP.load(WEIGHTS).bind(s)
+    ug = torch.tensor(u, device="cuda")
+    araw, _ = s.indicator(ug)
+    npos = int((araw > 0).sum())
+    print(f"elements with alpha > 0: {npos} of {s.nelem}")
+    assert 0 < npos < s.nelem // 2
+    nsteps = 4
+    a = [ug.clone(), s.new_state()]
+    da = s.new_dt()
+    s.prepare(a[0], da)
+    for n in range(nsteps):
+        s.advance(a[n % 2], a[(n + 1) % 2], da)
+    b = [ug.clone(), s.new_state()]
+    db = s.new_dt()
+    for n in range(nsteps):
+        s.step(b[n % 2], b[(n + 1) % 2], db)
+    torch.cuda.synchronize()
+    got, ref = a[nsteps % 2].cpu().numpy(), b[nsteps % 2].cpu().numpy()
+    rel = max(np.max(np.abs(got[v] - ref[v])) / np.max(np.abs(ref[v])) for v in range(ref.shape[0]))
+    print(f"pipelined vs crk_step with the network: {rel:.2e}")
+    assert rel <= 1e-13
