@@ -390,16 +390,22 @@ def test_deterministic(orc):
     assert torch.equal(outs[0], outs[1])
 
 
-def test_full_size_blended_pipelined(orc):
+@pytest.mark.parametrize("rough", ["everywhere", "lower_half"])
+def test_full_size_blended_pipelined(orc, rough):
     """The benchmarked KHI configuration (256x256, N = 3, Kennedy-Gruber,
     blending) in the pipelined launches, from a rough state (multiplicative
-    noise of 5 %) so that the indicator blends many elements: the raw
-    indicator and its smoothing come from the interface tail of the previous
-    step; three steps against the oracle's own three steps (its own dt and
-    alpha each step)."""
+    noise of 5 %, everywhere or in the lower half of the mesh only) so that
+    the indicator blends many elements: the raw indicator, its smoothing and
+    the tile flags come from the interface tail of the previous step; with
+    the lower half rough, flagged and clear tiles run side by side in the two
+    local-phase instances.  Three steps against the oracle's own three steps
+    (its own dt and alpha each step)."""
     p, s = _pair(orc, dim=2, nx=256, ny=256, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=1,
                  limiter=orc.LIM_BLEND_MODAL, nthreads=16)
-    u = inputs.perturb(inputs.kelvin_helmholtz(256, 256, orc.gll(3)[0]), 17, 5e-2)
+    u0 = inputs.kelvin_helmholtz(256, 256, orc.gll(3)[0])
+    u = inputs.perturb(u0, 17, 5e-2)
+    if rough == "lower_half":
+        u[:, 128 * 256:, :] = u0[:, 128 * 256:, :]
     ref, nblend = u, 0
     for _ in range(3):
         ref, alpha = orc.crk_step(p, ref, orc.compute_dt(p, ref))
@@ -411,8 +417,10 @@ def test_full_size_blended_pipelined(orc):
         s.advance(b[n % 2], b[(n + 1) % 2], dtp)
     torch.cuda.synchronize()
     got = b[1].cpu().numpy()
-    print(f"blended full size: alpha > 0 in up to {nblend} elements, rel={_rel(got, ref):.2e}")
+    print(f"blended full size ({rough}): alpha > 0 in up to {nblend} elements, rel={_rel(got, ref):.2e}")
     assert nblend > 1000
+    if rough == "lower_half":
+        assert nblend < 0.75 * p.nelem
     assert _rel(got, ref) <= TOL64
 
 
