@@ -40,6 +40,20 @@ __device__ __forceinline__ long xcd_tile(long b, long G)
     return x * q + (x < r ? x : r) + b / NXCD;
 }
 
+// Chunked variant for the local phase: each XCD takes chunks of XCD_CHUNK
+// consecutive tiles in turn (chunk c on XCD c mod NXCD), so that a region
+// of flagged tiles, which is contiguous in space, is spread over every XCD
+// instead of loading the few that own its part of the mesh; blocks past the
+// last whole round of chunks keep their own index.  A bijection on [0, G).
+constexpr long XCD_CHUNK = 16;
+__device__ __forceinline__ long xcd_chunk_tile(long b, long G)
+{
+    const long round = NXCD * XCD_CHUNK, gm = (G / round) * round;
+    if (b >= gm) return b;
+    const long x = b % NXCD, j = b / NXCD;
+    return ((j / XCD_CHUNK) * NXCD + x) * XCD_CHUNK + j % XCD_CHUNK;
+}
+
 // Everything a kernel needs besides its pointers; passed by value.
 struct Tables {
     int dim, nx, ny, N, M, nelem, nnode, nface;  // nface = nodes per face
@@ -749,7 +763,7 @@ __global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     constexpr int TB = tile_block<NP>();
     __shared__ real smem[LocalShape<real, EQ, DIM, N, FLUX>::slots * TB];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_chunk_tile(blockIdx.x, gridDim.x);
     if (a.tiles_in != nullptr) {
         const int flagged = a.tiles_in[tile];
         if constexpr (!BLEND) {
