@@ -92,24 +92,32 @@ def test_fr_rhs_parity(orc, dim, N, eq, vol, surf, nx, ny):
     assert np.all(err <= 1e-13 * scale)
 
 
-@pytest.mark.parametrize("dim", [1, 2])
-def test_fr_rhs_entropy_rate(orc, dim):
+@pytest.mark.parametrize("dim,eq", [(1, 0), (2, 0), (2, 1)])
+def test_fr_rhs_entropy_rate(orc, dim, eq):
+    """Euler with the Ranocha flux, GLM-MHD with the Derigs-form flux and the
+    local Powell/GLM term (faces: the same flux plus 1/2 B(u)(g^- + g^+))."""
     N, nx, ny = 3, 5, 4
-    p, s = _pair(orc, dim=dim, N=N, nx=nx, ny=ny, vol_flux=orc.VOL_RANOCHA)
     xi, w = orc.gll(N)
-    # nodal noise makes the traces of neighbouring elements differ
-    u = inputs.perturb(inputs.random_smooth_euler(nx, ny, xi, seed=7, dim=dim, amp=0.3), 8, 1e-2)
+    if eq == 1:
+        p, s = _pair(orc, dim=2, N=N, nx=nx, ny=ny, eq=orc.MHD, gamma=5.0 / 3.0, vol_flux=orc.VOL_DERIGS)
+        u = inputs.perturb(inputs.random_smooth_mhd(nx, ny, xi, seed=21, amp=0.25), 22, 1e-2)
+        p.ch = orc.compute_ch(p, u)
+    else:
+        p, s = _pair(orc, dim=dim, N=N, nx=nx, ny=ny, vol_flux=orc.VOL_RANOCHA)
+        # nodal noise makes the traces of neighbouring elements differ
+        u = inputs.perturb(inputs.random_smooth_euler(nx, ny, xi, seed=7, dim=dim, amp=0.3), 8, 1e-2)
     wq = w if dim == 1 else np.outer(w, w).ravel()
     ug = torch.tensor(u, device="cuda")
+    dt = torch.tensor([0.0, p.ch], dtype=torch.float64, device="cuda")
     for surf, conservative in ((crk.SURF_EC, True), (crk.SURF_RUSANOV, False)):
-        r = s.fr_rhs(ug, surface=surf).cpu().numpy()
+        r = s.fr_rhs(ug, surface=surf, dt=dt).cpu().numpy()
         rate, scale = 0.0, 0.0
         for e in range(p.nelem):
             for q in range(p.nnode):
                 wv = orc.entropy_vars(p, u[:, e, q])
                 rate += wq[q] * wv @ r[:, e, q]
                 scale += wq[q] * np.abs(wv) @ np.abs(r[:, e, q])
-        print(f"dim={dim} surface={surf}: rate={rate:.3e} scale={scale:.3e}")
+        print(f"dim={dim} eq={eq} surface={surf}: rate={rate:.3e} scale={scale:.3e}")
         if conservative:
             assert abs(rate) < 1e-13 * scale
         else:
