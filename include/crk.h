@@ -27,8 +27,9 @@
  *    or float (CRK_FP32).
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default
  *    stream) and runs asynchronously; argument checks are synchronous.
- *    Nothing reads back to the host, so the calls can be captured in a HIP
- *    graph.  Calls that share a workspace must not run concurrently.
+ *    Apart from crk_check, nothing reads back to the host, so the calls can
+ *    be captured in a HIP graph.  Calls that share a workspace must not run
+ *    concurrently.
  *  - dt_dev points to 2 device doubles: dt_dev[0] = time step,
  *    dt_dev[1] = GLM cleaning speed c_h (MHD; 0 for Euler).
  */
@@ -47,6 +48,8 @@ typedef enum {
     CRK_ERR_ARG = -1,          /* invalid argument (null, size, alias)          */
     CRK_ERR_UNSUPPORTED = -2,  /* configuration not compiled in                 */
     CRK_ERR_HIP = -3,          /* a HIP runtime call or kernel launch failed    */
+    CRK_ERR_NONPHYSICAL = -4,  /* crk_check: rho <= 0 or p <= 0 somewhere       */
+    CRK_ERR_NOT_FINITE = -5,   /* crk_check: a value is NaN or infinite         */
     CRK_ERR_STATE = -6         /* missing workspace or wrong call order         */
 } crk_status;
 
@@ -211,6 +214,13 @@ crk_status crk_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev
  * again (CRK_ERR_STATE). */
 #define CRK_PHASE_LOCAL 1
 #define CRK_PHASE_INTERFACE 2
+/* The local phase in its two launches, for timing each on its own: the
+ * element tiles where no blending coefficient can be positive run a kernel
+ * instance without the blending code (PLAIN), the others the instance with
+ * it (BLEND).  CRK_PHASE_LOCAL = both; issued separately, PLAIN comes first
+ * and both come before the interface phase. */
+#define CRK_PHASE_LOCAL_PLAIN 4
+#define CRK_PHASE_LOCAL_BLEND 8
 crk_status crk_prepare(crk_solver *s, const void *u, double *dt_dev, crk_stream stream);
 crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, int phases, crk_stream stream);
 
@@ -228,6 +238,16 @@ crk_status crk_run(crk_solver *s, void *u0, void *u1, double *dt_dev, int nsteps
  * min rho, min p, count of non-finite values, first element index that is
  * non-finite or has rho <= 0 or p <= 0 (-1 if none).  Needs the workspace. */
 crk_status crk_diagnostics(crk_solver *s, const void *u, double *out_dev, crk_stream stream);
+
+/* Crash detection on the host: the diagnostics of u (as crk_diagnostics,
+ * into the workspace), waited for on `stream` and read back.  Returns
+ * CRK_ERR_NOT_FINITE if a value of u is NaN or infinite, else
+ * CRK_ERR_NONPHYSICAL if rho <= 0 or p <= 0 at some node, else CRK_OK; in
+ * every case *first_bad (if non-NULL) = the first element index that is
+ * non-finite or non-physical (-1 if none) and diag_host (if non-NULL, nvar
+ * + 5 host doubles) receives the diagnostics.  Synchronises `stream`, so it
+ * cannot be captured in a HIP graph.  Needs the workspace. */
+crk_status crk_check(crk_solver *s, const void *u, int64_t *first_bad, double *diag_host, crk_stream stream);
 
 /* ---------------------------------------------------------------- learned indicator
  * A multilayer perceptron 16 -> 64 -> 64 -> 1 (ReLU; output alpha_max *
@@ -255,7 +275,9 @@ crk_status crk_mlp_adam(int64_t count, float *theta, float *m, float *v, const f
 crk_status crk_mlp_to_bf16(int64_t count, const float *theta, uint16_t *theta_bf16, crk_stream stream);
 /* Features of the state u (FP32): features[e][node] = 1 + log10(max(f,
  * 1e-16))/16 with f = m_kl^2 / sum m^2 the modal energy fractions of rho*p
- * (in [0, 1]).  Needs the workspace. */
+ * (in [0, 1]).  Needs the workspace; overwrites the indicator that the
+ * pipelined calls keep there, so crk_advance and crk_run return
+ * CRK_ERR_STATE until crk_prepare runs again. */
 crk_status crk_features(crk_solver *s, const void *u, float *features, crk_stream stream);
 /* Training labels (1/0 per element, FP32) of the unlimited update u_high
  * of u_n: 1 if at a node of the element rho or p leaves
@@ -300,8 +322,9 @@ crk_status crk_batch_bind(crk_batch *b, void *u0, void *u1, double *dt_dev, void
                           crk_stream stream);
 /* dt of every problem from state src (0: u0, 1: u1). */
 crk_status crk_batch_prepare(crk_batch *b, int src, crk_stream stream);
-/* One pipelined step from state src into the other buffer (phases as for
- * crk_advance); leaves the dt of the new states in dt_dev. */
+/* One pipelined step from state src into the other buffer (phases:
+ * CRK_PHASE_LOCAL and/or CRK_PHASE_INTERFACE, as for crk_advance); leaves the
+ * dt of the new states in dt_dev. */
 crk_status crk_batch_advance(crk_batch *b, int src, int phases, crk_stream stream);
 /* Capture two steps u0 -> u1 -> u0 into a HIP graph (stream must not be the
  * default stream), and replay it. */

@@ -21,8 +21,9 @@ VOL_CENTRAL, VOL_KG, VOL_RANOCHA, VOL_DERIGS = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 LIM_NONE, LIM_BLEND = 0, 1
 SURF_RUSANOV, SURF_EC = 0, 1
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NONPHYSICAL, ERR_NOT_FINITE, ERR_STATE = 0, -1, -2, -3, -4, -5, -6
 STEP_COMPUTE_DT = 1
-PHASE_LOCAL, PHASE_INTERFACE = 1, 2
+PHASE_LOCAL, PHASE_INTERFACE, PHASE_LOCAL_PLAIN, PHASE_LOCAL_BLEND = 1, 2, 4, 8
 
 
 class MeshDesc(C.Structure):
@@ -78,6 +79,7 @@ def lib():
             "crk_run": (st, [_vp, _vp, _vp, _vp, C.c_int, _vp]),
             "crk_step": (st, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp]),
             "crk_diagnostics": (st, [_vp, _vp, _vp, _vp]),
+            "crk_check": (st, [_vp, _vp, C.POINTER(C.c_int64), _dp, _vp]),
             "crk_prepare": (st, [_vp, _vp, _vp, _vp]),
             "crk_advance": (st, [_vp, _vp, _vp, _vp, C.c_int, _vp]),
             "crk_last_error": (C.c_char_p, []),
@@ -247,6 +249,20 @@ class Solver:
         out = torch.empty(self.shape[0] + 5, dtype=torch.float64, device=self.device)
         _check(lib().crk_diagnostics(self._h, _ptr(u), _ptr(out), _stream(stream)), "crk_diagnostics")
         return out
+
+
+    def check(self, u, stream=None):
+        """Crash detection (crk_check): (status, first bad element, FP64
+        diagnostics as a host array).  status is OK, ERR_NOT_FINITE or
+        ERR_NONPHYSICAL; other statuses raise.  Waits for the stream."""
+        import numpy as np
+        self._check_state(u)
+        fb = C.c_int64()
+        d = np.zeros(self.shape[0] + 5)
+        rc = lib().crk_check(self._h, _ptr(u), C.byref(fb), d.ctypes.data_as(_dp), _stream(stream))
+        if rc not in (OK, ERR_NOT_FINITE, ERR_NONPHYSICAL):
+            _check(rc, "crk_check")
+        return rc, fb.value, d
 
 
 class BatchTuning(C.Structure):

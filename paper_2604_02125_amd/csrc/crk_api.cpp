@@ -125,7 +125,7 @@ struct crk_solver {
     Tables t;
     size_t elem_bytes;
     size_t state_bytes, trace_bytes;
-    size_t off_partials, off_slots, off_araw, off_alpha, off_features, off_tiles, off_traces, ws_bytes;
+    size_t off_partials, off_slots, off_araw, off_alpha, off_features, off_tiles, off_diag, off_traces, ws_bytes;
     long ntiles;     // local-phase tiles (two flag sets of ntiles ints in the workspace)
     int tparity;     // flag set of the next local phase
     bool tiles_valid; // the flag set covers the raw coefficients in the workspace
@@ -323,6 +323,7 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     s->off_features = off; off = align256(off + sizeof(float) * nelem * nnode);
     s->ntiles = elem_blocks;
     s->off_tiles = off; off = align256(off + sizeof(int) * 2 * elem_blocks);
+    s->off_diag = off; off = align256(off + sizeof(double) * (t.M + 5));
     s->off_traces = off; off = align256(off + s->trace_bytes);
     s->ws_bytes = off;
     s->ws = nullptr;
@@ -374,6 +375,25 @@ crk_status crk_set_workspace(crk_solver *s, void *dev, size_t bytes)
     s->prepared = false;
     return CRK_OK;
 }
+
+} // extern "C"
+
+namespace crk {
+// CFL time step of u with caller-chosen storage for the reduction partials
+// (for entry points outside this file); at most max_parts partials are used,
+// else CRK_ERR_ARG before anything is launched.
+crk_status solver_dt(crk_solver *s, const void *u, double *parts, int max_parts, double *dt_dev, hipStream_t stream)
+{
+    if (!s) return fail(CRK_ERR_ARG, "null solver");
+    if (!u || !dt_dev || !parts) return fail(CRK_ERR_ARG, "null pointer");
+    if (reduction_blocks(s->t) > max_parts) return fail(CRK_ERR_ARG, "more reduction partials than the scratch holds");
+    hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::dt(s->t, u, parts, dt_dev, stream); });
+    return e == hipSuccess ? CRK_OK : hip_fail(e, "compute dt");
+}
+crk_status fail_with(crk_status st, const char *msg) { return fail(st, msg); }
+} // namespace crk
+
+extern "C" {
 
 crk_status crk_compute_dt(crk_solver *s, const void *u, double *dt_dev, crk_stream stream)
 {
@@ -433,6 +453,11 @@ crk_status crk_features(crk_solver *s, const void *u, float *features, crk_strea
     if (!u || !features) return fail(CRK_ERR_ARG, "null argument");
     if (s->mesh.equation != CRK_EULER) return fail(CRK_ERR_UNSUPPORTED, "features are defined for Euler only");
     double *araw = (double *)(s->ws + s->off_araw);
+    // the workspace's raw coefficients now describe u, not the state of a
+    // pipelined sequence: crk_advance needs crk_prepare again, and the next
+    // local phase may not trust the tile flags
+    s->prepared = false;
+    s->tiles_valid = false;
     hipError_t e = dispatch(s, [&](auto fam) {
         return decltype(fam)::indicator(s->t, u, araw, nullptr, features, (hipStream_t)stream);
     });
@@ -563,7 +588,8 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
     if (!u_in || !u_out || !dt_dev) return fail(CRK_ERR_ARG, "null pointer");
     if (u_in == u_out) return fail(CRK_ERR_ARG, "u_in and u_out must not alias");
     if (!is_aligned(u_in) || !is_aligned(u_out)) return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
-    if (phases & ~(CRK_PHASE_LOCAL | CRK_PHASE_INTERFACE)) return fail(CRK_ERR_ARG, "unknown phase bits");
+    if (phases & ~(CRK_PHASE_LOCAL | CRK_PHASE_INTERFACE | CRK_PHASE_LOCAL_PLAIN | CRK_PHASE_LOCAL_BLEND))
+        return fail(CRK_ERR_ARG, "unknown phase bits");
     if (!s->prepared) return fail(CRK_ERR_STATE, "crk_prepare must run before crk_advance");
     const bool lim = s->limiter == CRK_LIM_BLEND;
     double *araw = (double *)(s->ws + s->off_araw);
@@ -574,8 +600,11 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
     int *tiles = (int *)(s->ws + s->off_tiles);
     int *t_cur = tiles + (size_t)s->tparity * s->ntiles, *t_next = tiles + (size_t)(1 - s->tparity) * s->ntiles;
     hipError_t e = hipSuccess;
-    if (phases & CRK_PHASE_LOCAL) {
+    const int instances = ((phases & CRK_PHASE_LOCAL) ? 3 : 0) | ((phases & CRK_PHASE_LOCAL_PLAIN) ? 1 : 0) |
+                          ((phases & CRK_PHASE_LOCAL_BLEND) ? 2 : 0);
+    if (instances) {
         StepPtrs p{};
+        p.instances = instances;
         p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = tr;
         p.alpha_raw = lim ? araw : nullptr;
         p.alpha_s = alpha;
@@ -654,6 +683,38 @@ crk_status crk_diagnostics(crk_solver *s, const void *u, double *out_dev, crk_st
     double *parts = (double *)(s->ws + s->off_partials);
     hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::diag(s->t, u, parts, out_dev, (hipStream_t)stream); });
     return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_diagnostics");
+}
+
+crk_status crk_check(crk_solver *s, const void *u, int64_t *first_bad, double *diag_host, crk_stream stream)
+{
+    if (first_bad) *first_bad = -1;
+    crk_status st = need_ws(s);
+    if (st) return st;
+    if (!u) return fail(CRK_ERR_ARG, "null state");
+    if (!is_aligned(u)) return fail(CRK_ERR_ARG, "state must be 256-byte aligned");
+    const int M = s->t.M;
+    double *dev = (double *)(s->ws + s->off_diag);
+    st = crk_diagnostics(s, u, dev, stream);
+    if (st) return st;
+    double h[9 + 5];
+    hipError_t e = hipMemcpyAsync(h, dev, sizeof(double) * (M + 5), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "crk_check");
+    if (diag_host) std::memcpy(diag_host, h, sizeof(double) * (M + 5));
+    const double nonfinite = h[M + 3], first = h[M + 4];
+    if (first_bad) *first_bad = (int64_t)first;
+    if (nonfinite > 0.0) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "%.0f non-finite values; first bad element %.0f", nonfinite, first);
+        return fail(CRK_ERR_NOT_FINITE, buf);
+    }
+    if (first >= 0.0) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "rho <= 0 or p <= 0 (min rho %.3e, min p %.3e); first bad element %.0f",
+                      h[M + 1], h[M + 2], first);
+        return fail(CRK_ERR_NONPHYSICAL, buf);
+    }
+    return CRK_OK;
 }
 
 } // extern "C"

@@ -117,6 +117,10 @@ struct StepPtrs {
     // flags of u_out are marked into tiles_out.  nullptr: no flags.
     const int *tiles_in;
     int *tiles_out;
+    // local phase: which instances to launch, bit 0 the one without the
+    // blending code, bit 1 the one with it (0: both); either launches only
+    // where the configuration uses it
+    int instances;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -874,26 +878,32 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
         if (al > 1.0 - t.alpha_min) al = 1.0;
         if (al > t.alpha_max) al = t.alpha_max;
         if (node == 0) alpha_raw[e] = al;
-        // tile flags (2D): lane j < 13 of a blending element flags the tile
-        // of the j-th element within two faces of it (the element, its four
-        // face neighbours, the four at distance two along x or y and the
-        // four diagonal ones), periodic
+        // tile flags (2D): the lanes of a blending element flag the tiles of
+        // the 13 elements within two faces of it (the element, its four face
+        // neighbours, the four at distance two along x or y and the four
+        // diagonal ones), periodic; target j is taken by lane j mod NP, so
+        // elements of fewer than 13 nodes (N = 1, 2) cover all of them too
         if constexpr (DIM == 2) {
-            if (tiles != nullptr && al > 0.0 && node < 13) {
-                const int r = node < 9 ? (node - 1) & 3 : node - 9;
-                int dx = 0, dy = 0;
-                if (node >= 1 && node <= 8) {
-                    const int s = node <= 4 ? 1 : 2;
-                    dx = r == 0 ? s : (r == 1 ? -s : 0);
-                    dy = r == 2 ? s : (r == 3 ? -s : 0);
-                } else if (node >= 9) {
-                    dx = (r & 1) ? 1 : -1;
-                    dy = (r & 2) ? 1 : -1;
-                }
+            if (tiles != nullptr && al > 0.0) {
                 const int nx = t.nx, ny = t.ny, ei = (int)e;
                 const int ey = ei / nx, ex = ei - ey * nx;
-                const int x = ((ex + dx) % nx + nx) % nx, y = ((ey + dy) % ny + ny) % ny;
-                tiles[(y * nx + x) / (BLK / NP)] = 1;
+#pragma unroll
+                for (int j0 = 0; j0 < 13; j0 += NP) {
+                    const int j = j0 + node;
+                    if (j >= 13) break;
+                    const int r = j < 9 ? (j - 1) & 3 : j - 9;
+                    int dx = 0, dy = 0;
+                    if (j >= 1 && j <= 8) {
+                        const int s = j <= 4 ? 1 : 2;
+                        dx = r == 0 ? s : (r == 1 ? -s : 0);
+                        dy = r == 2 ? s : (r == 3 ? -s : 0);
+                    } else if (j >= 9) {
+                        dx = (r & 1) ? 1 : -1;
+                        dy = (r & 2) ? 1 : -1;
+                    }
+                    const int x = ((ex + dx) % nx + nx) % nx, y = ((ey + dy) % ny + ny) % ny;
+                    tiles[(y * nx + x) / (BLK / NP)] = 1;
+                }
             }
         }
     }
@@ -1384,13 +1394,14 @@ hipError_t launch_local(const Tables &t, const StepPtrs &p, hipStream_t s)
     // instance without the blending code; with tile flags both run, the
     // blending one second; with given coefficients only the blending one
     const bool blend = p.alpha != nullptr || p.alpha_raw != nullptr;
-    if (!blend || p.tiles_in != nullptr) {
+    const int which = p.instances ? p.instances : 3;
+    if ((which & 1) && (!blend || p.tiles_in != nullptr)) {
         CRK_LOCAL_LAUNCH(false)
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if constexpr (EQ == EQ_EULER) {
-        if (blend) {
+        if ((which & 2) && blend) {
             CRK_LOCAL_LAUNCH(true)
         }
     }

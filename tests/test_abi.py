@@ -100,6 +100,28 @@ def test_calls_without_workspace_fail_cleanly():
     crk.lib().crk_destroy(h)
 
 
+def test_check_validation():
+    """crk_check (crash detection) validates before it launches or reads back:
+    a null solver, no workspace, a null or misaligned state."""
+    L = crk.lib()
+    fb = C.c_int64(123)
+    assert L.crk_check(None, C.c_void_p(256), C.byref(fb), None, None) == crk.ERR_ARG
+    assert fb.value == -1
+    m = crk.MeshDesc(2, 4, 4, 0.0, 1.0, 0.0, 1.0, 3, crk.CRK_EULER, 1.4, crk.FP64)
+    sc = crk.SchemeDesc()
+    sc.volume_flux, sc.cfl = crk.VOL_KG, 0.4
+    h = C.c_void_p()
+    assert L.crk_create(C.byref(m), C.byref(sc), C.byref(h)) == 0
+    assert L.crk_check(h, C.c_void_p(256), C.byref(fb), None, None) == crk.ERR_STATE
+    nb = C.c_size_t()
+    assert L.crk_workspace_bytes(h, C.byref(nb)) == 0
+    assert L.crk_set_workspace(h, C.c_void_p(1 << 20), nb.value) == 0
+    assert L.crk_check(h, None, C.byref(fb), None, None) == crk.ERR_ARG
+    assert L.crk_check(h, C.c_void_p(264), C.byref(fb), None, None) == crk.ERR_ARG
+    assert "aligned" in L.crk_last_error().decode()
+    L.crk_destroy(h)
+
+
 def test_fr_rhs_validation():
     # the semi-discrete test operator validates its arguments before any launch
     L = crk.lib()

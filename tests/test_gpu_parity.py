@@ -378,6 +378,34 @@ def test_diagnostics_parity(orc):
     assert d[M + 1] == o["min_rho"] and abs(d[M + 2] - o["min_p"]) <= 1e-14 * o["min_p"] and d[M + 4] == -1
 
 
+@pytest.mark.parametrize("eq", [0, 1])
+def test_check_statuses(orc, eq):
+    """crk_check reads the diagnostics back: a state with a NaN returns
+    CRK_ERR_NOT_FINITE, one with a negative pressure CRK_ERR_NONPHYSICAL, each
+    with the first bad element (the oracle's), a clean state CRK_OK."""
+    if eq == 1:
+        p, s = _pair(orc, dim=2, nx=9, ny=7, N=4, eq=orc.MHD, gamma=5.0 / 3.0, vol_flux=3)
+        E = 4
+    else:
+        p, s = _pair(orc, dim=2, nx=13, ny=11, N=3, vol_flux=1)
+        E = 3
+    u = _state(orc, p, seed=46)
+    rc, fb, d = s.check(torch.tensor(u, device="cuda"))
+    assert rc == crk.OK and fb == -1 and d[p.nvar + 4] == -1
+    bad = u.copy()
+    bad[E, 23, 3] = -10.0           # energy below the kinetic (and magnetic) part: p < 0
+    rc, fb, d = s.check(torch.tensor(bad, device="cuda"))
+    assert rc == crk.ERR_NONPHYSICAL and fb == 23 == orc.diagnostics(p, bad)["first_bad"]
+    assert "first bad element 23" in crk.lib().crk_last_error().decode()
+    bad[1, 31, 0] = np.inf
+    bad[0, 50, 7] = np.nan
+    rc, fb, d = s.check(torch.tensor(bad, device="cuda"))
+    assert rc == crk.ERR_NOT_FINITE and fb == 23 and d[p.nvar + 3] == 2
+    bad[E, 23, 3] = u[E, 23, 3]
+    rc, fb, d = s.check(torch.tensor(bad, device="cuda"))
+    assert rc == crk.ERR_NOT_FINITE and fb == 31 == orc.diagnostics(p, bad)["first_bad"]
+
+
 def test_deterministic(orc):
     p, s = _pair(orc, dim=2, nx=32, ny=32, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=1,
                  limiter=orc.LIM_BLEND_MODAL)
@@ -491,8 +519,8 @@ def test_full_size_mhd_parity(orc):
     assert rel <= TOL64
 
 
-@pytest.mark.parametrize("case", ["khi_blend", "khi_blend_N2", "khi_blend_ranocha", "khi_blend_kg_N4", "euler2d_N1",
-                                  "euler1d", "mhd"])
+@pytest.mark.parametrize("case", ["khi_blend", "khi_blend_N2", "khi_blend_ranocha", "khi_blend_kg_N4", "khi_blend_kg_N1",
+                                  "khi_blend_kg_N2", "euler2d_N1", "euler1d", "mhd"])
 def test_pipelined_advance(orc, case):
     """crk_prepare + crk_advance (CFL reduction and indicator fused into the
     interface phase) against the oracle trajectory and against crk_step."""
@@ -510,6 +538,13 @@ def test_pipelined_advance(orc, case):
     elif case == "khi_blend_N2":
         p, s = _pair(orc, dim=2, nx=27, ny=22, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=2, vol_flux=2,
                      limiter=orc.LIM_BLEND_MODAL)
+    elif case in ("khi_blend_kg_N1", "khi_blend_kg_N2"):
+        # tile flags with elements of fewer nodes than the 13 tiles a blending
+        # element flags (4 and 9 lanes); tiles of 16 (N=1) and 28 (N=2)
+        # elements, nx a multiple of neither
+        NN = 1 if case.endswith("N1") else 2
+        p, s = _pair(orc, dim=2, nx=27, ny=22, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=NN, vol_flux=1,
+                     limiter=orc.LIM_BLEND_MODAL)
     elif case == "euler2d_N1":
         p, s = _pair(orc, dim=2, nx=29, ny=17, N=1, vol_flux=1)
     elif case == "euler1d":
@@ -517,6 +552,10 @@ def test_pipelined_advance(orc, case):
     else:
         p, s = _pair(orc, dim=2, nx=10, ny=9, N=4, eq=orc.MHD, gamma=5.0 / 3.0, vol_flux=3)
     u = _state(orc, p, seed=51)
+    if case in ("khi_blend_kg_N1", "khi_blend_kg_N2"):
+        # rough lower half: blending and clear tiles side by side
+        r = inputs.perturb(u, 17, 0.05)
+        u[:, : (p.ny // 2) * p.nx, :] = r[:, : (p.ny // 2) * p.nx, :]
     nsteps = 5
     ref = u.copy()
     for _ in range(nsteps):
@@ -553,6 +592,16 @@ def test_pipelined_advance(orc, case):
         s.advance(b3[n % 2], b3[(n + 1) % 2], d3, phases=crk.PHASE_INTERFACE)
     torch.cuda.synchronize()
     assert torch.equal(b3[nsteps % 2], buf[nsteps % 2])
+    # the local phase in its two launches (the instance without the blending
+    # code, then the one with it), as the benchmark times them
+    b4 = [ug.clone(), s.new_state()]
+    d4 = s.new_dt()
+    s.prepare(b4[0], d4)
+    for n in range(nsteps):
+        for ph in (crk.PHASE_LOCAL_PLAIN, crk.PHASE_LOCAL_BLEND, crk.PHASE_INTERFACE):
+            s.advance(b4[n % 2], b4[(n + 1) % 2], d4, phases=ph)
+    torch.cuda.synchronize()
+    assert torch.equal(b4[nsteps % 2], buf[nsteps % 2])
 
 
 @pytest.mark.parametrize("case", ["wave1d_fused", "wave1d_blend_fused", "khi2d_loop", "odd_steps"])
