@@ -96,7 +96,7 @@ def test_calls_without_workspace_fail_cleanly():
     assert crk.lib().crk_set_workspace(h, C.c_void_p(1 << 20), nb.value) == 0
     assert crk.lib().crk_advance(h, C.c_void_p(256), C.c_void_p(4096), C.c_void_p(768), 3, None) == -6
     assert crk.lib().crk_run(h, C.c_void_p(256), C.c_void_p(4096), C.c_void_p(768), 5, None) == -6
-    assert crk.lib().crk_advance(h, C.c_void_p(256), C.c_void_p(4096), C.c_void_p(768), 4, None) == -1
+    assert crk.lib().crk_advance(h, C.c_void_p(256), C.c_void_p(4096), C.c_void_p(768), 16, None) == -1
     crk.lib().crk_destroy(h)
 
 
