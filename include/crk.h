@@ -137,6 +137,17 @@ crk_status crk_reference_element(int degree, double *xi, double *w, double *D);
  * dt_dev[1] = c_h = max_{e,p,d} (|v_d| + c_f) (MHD).  Needs the workspace. */
 crk_status crk_compute_dt(crk_solver *s, const void *u, double *dt_dev, crk_stream stream);
 
+/* As crk_compute_dt, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): needs no workspace and allocates nothing.  The reduction
+ * partials go to a static scratch array of the library (8 KiB per GPU,
+ * enough for every mesh the library accepts: the reduction uses at most 1024
+ * partials; CRK_ERR_ARG beyond that).  Every call on a GPU shares that GPU's
+ * scratch, so calls that overlap on one GPU (concurrent streams, threads)
+ * race; stream-ordered calls do not.  The scratch keeps the previous call's
+ * partials, which a call never reads (it writes every partial it uses). */
+crk_status crk_compute_dt_noalloc(crk_solver *s, const void *u, double *dt_dev, crk_stream stream);
+
 /* Blending coefficients of the subcell-FV limiter (Hennemann-Gassner modal
  * energy of rho*p, clipped at alpha_min, capped at alpha_max):
  * alpha_raw[e], and alpha[e] = max(alpha_raw[e], max over face neighbours
