@@ -31,21 +31,43 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 
-# Per local phase of the KHI 256^2 FP64 workload (with the Kennedy-Gruber flux
-# both k_local instances, the one for flagged tiles and the one for the rest),
-# from rocprofv3 --pmc:
-# HBM bytes = FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB, scaled by the plain-copy
-# calibration) and FP64 FLOPs = SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes; valid only
-# for the kernel sources whose digest is recorded with them.
-MEASURED_TRAFFIC = {
-    ("khi256", "fp64"): {"sources_sha256": "8008dc124bbbdf6eb170a2289eefd6911f4b04ef836f339e2a0b7349b76002d8",
-                         "bytes": (2.0 * 22854.4 + 1.0 * 66112.0) * 1024,
-                         "fp64_flops": 15433728.0 * 64},
-    ("khi256_ranocha", "fp64"): {"sources_sha256": "8008dc124bbbdf6eb170a2289eefd6911f4b04ef836f339e2a0b7349b76002d8",
-                                 "bytes": (2.0 * 23608.1 + 1.0 * 66048.0) * 1024,
-                                 "fp64_flops": 38551552.0 * 64},
-}
+# Counter figures (HBM bytes from FETCH_SIZE/WRITE_SIZE, executed FLOPs from
+# SQ_INSTS_VALU_FLOPS_FP64/FP32) are not measured by this script: they come
+# from the rocprofv3 summaries under profiles/, each of which carries one
+# machine-readable "counters:" line per profiled workload and the digest of
+# the kernel sources it was taken with.  A figure is used only when that
+# digest matches the sources of this checkout; otherwise it is null.
 KERNEL_SOURCES = ("paper_2604_02125_amd/csrc/crk_kernels.hpp", "paper_2604_02125_amd/csrc/crk_physics.hpp")
+
+
+def profiled_counters(workload: str):
+    """The counters line of profiles/*.md for `workload` taken with the
+    current kernel sources, or None."""
+    import glob
+    dig = sources_digest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(f) as fh:
+            for line in fh:
+                if line.startswith("counters: "):
+                    rec = json.loads(line[len("counters: "):])
+                    if rec.get("workload") == workload and rec.get("sources_sha256") == dig:
+                        rec["profile"] = os.path.relpath(f, ROOT)
+                        return rec
+    return None
+
+
+# Formula (algorithmic) FLOPs of the local-stage kernel per DOF-update:
+# add/mul/div = 1, FMA = 2, log/sqrt = 1, each unordered node pair counted
+# once.  Per stage and node: dim*N/2 unordered pairs (two-point flux plus
+# accumulation into the M residual components), the per-node fields, and
+# the stage update (4 M).  The executed count is higher (reciprocal and log
+# sequences, mirrored pairs); the counters give that one.
+PAIR_FLOPS = {0: 24, 1: 33, 2: 60, 3: 136}      # central, Kennedy-Gruber, Ranocha, Derigs MHD
+NODE_FLOPS = {0: 20, 1: 10, 2: 12, 3: 183}
+
+
+def k2_formula_flops_per_dof(flux: int, N: int, dim: int, stages: int, M: int) -> float:
+    return stages * (dim * N / 2.0 * PAIR_FLOPS[flux] + NODE_FLOPS[flux] + 4 * M)
 
 
 def sources_digest() -> str:
@@ -62,15 +84,35 @@ KHI = dict(dim=2, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, degree=3, volume_flux=1, cfl
 
 
 def k2_bytes_per_dof(M: int, dim: int, N: int, elem: int) -> float:
-    """Algorithmic (unique) HBM bytes of the local-stage kernel per DOF: read
-    u^n and write the provisional state (M values per node); per face node
-    (2*dim faces of (N+1)^(dim-1) nodes per element) write the element's
-    share of the interface flux (M values) and read one wave speed: each
-    face node's two speeds are read by both elements of the face, so one
-    value per element and face node is unique."""
+    """Algorithmic HBM bytes of the local-stage phase per DOF for the general
+    trace design: read u^n, write the provisional state (M values per node),
+    and per face node (2*dim faces of (N+1)^(dim-1) nodes per element) write
+    three traces of M values (U, F and u^n), written once and read once by
+    the interface phase.  For the KHI workload: 64 + 96 = 160 B/DOF."""
+    npe = (N + 1) ** dim
+    face_nodes = 2 * dim * (N + 1) ** (dim - 1)
+    return elem * (2 * M + 3 * M * face_nodes / npe)
+
+
+def k2_design_bytes_per_dof(M: int, dim: int, N: int, elem: int) -> float:
+    """Algorithmic (unique) HBM bytes of this library's local-stage kernel per
+    DOF: read u^n and write the provisional state (M values per node); per
+    face node write the element's share of the interface flux (M values) and
+    read one wave speed (each face node's two speeds are read by both
+    elements of the face, so one value per element and face node is
+    unique).  For the KHI workload: 104 B/DOF."""
     npe = (N + 1) ** dim
     face_nodes = 2 * dim * (N + 1) ** (dim - 1)
     return elem * (2 * M + (M + 1) * face_nodes / npe)
+
+
+def step_bytes_per_dof(M: int, dim: int, N: int, elem: int) -> float:
+    """Algorithmic HBM bytes of one whole step per DOF: state read and
+    written once (2 M values per node) plus the three M-value traces of
+    every face node written once and read once.  KHI: 64 + 192 = 256 B/DOF."""
+    npe = (N + 1) ** dim
+    face_nodes = 2 * dim * (N + 1) ** (dim - 1)
+    return elem * (2 * M + 2 * 3 * M * face_nodes / npe)
 
 
 def rel_l2(a, b):
@@ -107,32 +149,39 @@ class Pipelined:
         self.n = 0
         crk._check(crk.lib().crk_prepare(self.s._h, crk._ptr(self.buf[0]), crk._ptr(self.dt), self.sp), "prepare")
 
-    def step(self):
+    def step(self, events=None):
+        """One pipelined step; with events (four torch.cuda.Event), record
+        them around the local phase's two launches and the interface phase."""
         crk, L = self.crk, self.crk.lib()
         ui, uo = self.buf[self.n % 2], self.buf[(self.n + 1) % 2]
         p = crk._ptr
-        crk._check(L.crk_advance(self.s._h, p(ui), p(uo), p(self.dt), crk.PHASE_LOCAL, self.sp), "advance/local")
-        crk._check(L.crk_advance(self.s._h, p(ui), p(uo), p(self.dt), crk.PHASE_INTERFACE, self.sp), "advance/iface")
+        h, a, b, d = self.s._h, p(ui), p(uo), p(self.dt)
+        if events is None:
+            crk._check(L.crk_advance(h, a, b, d, crk.PHASE_LOCAL, self.sp), "advance/local")
+            crk._check(L.crk_advance(h, a, b, d, crk.PHASE_INTERFACE, self.sp), "advance/iface")
+        else:
+            events[0].record(self.stream)
+            crk._check(L.crk_advance(h, a, b, d, crk.PHASE_LOCAL_PLAIN, self.sp), "advance/local plain")
+            events[1].record(self.stream)
+            crk._check(L.crk_advance(h, a, b, d, crk.PHASE_LOCAL_BLEND, self.sp), "advance/local blend")
+            events[2].record(self.stream)
+            crk._check(L.crk_advance(h, a, b, d, crk.PHASE_INTERFACE, self.sp), "advance/iface")
+            events[3].record(self.stream)
         self.n += 1
-
-    def local_phase(self):
-        """The local phase of the next step alone (leaves the step undone)."""
-        crk, L = self.crk, self.crk.lib()
-        ui, uo = self.buf[self.n % 2], self.buf[(self.n + 1) % 2]
-        p = crk._ptr
-        crk._check(L.crk_advance(self.s._h, p(ui), p(uo), p(self.dt), crk.PHASE_LOCAL, self.sp), "advance/local")
 
     @property
     def state(self):
         return self.buf[self.n % 2]
 
 
-def timed(pipe, steps, warmup, events=False, reps=20, settle=0.3):
-    """Wall time of `steps` pipelined steps; with events, then the mean
-    duration of the local-stage kernel from HIP events on the launch stream
-    around `reps` back-to-back local phases of the current state (the local
-    phase only reads u_in, so repeating it is the same launch each time;
-    events around single launches would add their own cost to each)."""
+def timed(pipe, steps, warmup, events=False, settle=0.3):
+    """Wall time of `steps` pipelined steps (no events inside).  With events,
+    the same steps are then run again from the initial state with HIP events
+    on the launch stream between the launches of every step, which gives the
+    average duration of the local phase's instance without the blending code
+    (the dominant kernel: every tile of a state where no coefficient is
+    positive), of the instance with it, and of the interface phase (its
+    kernel and the dt slots kernel), in milliseconds."""
     import torch
     # settle: keep the GPU busy with the same steps for a few tenths of a
     # second first, so that the timed steps see the clocks of a running
@@ -151,17 +200,20 @@ def timed(pipe, steps, warmup, events=False, reps=20, settle=0.3):
         pipe.step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    k2 = None
-    if events:
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        pipe.local_phase()
-        a.record(pipe.stream)
-        for _ in range(reps):
-            pipe.local_phase()
-        b.record(pipe.stream)
-        b.synchronize()
-        k2 = a.elapsed_time(b) / reps
-    return el, k2
+    if not events:
+        return el, None
+    n = pipe.n
+    pipe.reset()
+    for _ in range(warmup):
+        pipe.step()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for k in range(steps):
+        pipe.step(ev[k])
+    torch.cuda.synchronize()
+    assert pipe.n == n
+    mean = lambda i, j: sum(e[i].elapsed_time(e[j]) for e in ev) / steps
+    return el, {"k_local_plain_ms": mean(0, 1), "k_local_blend_ms": mean(1, 2), "interface_ms": mean(2, 3),
+                "local_phase_ms": mean(0, 2)}
 
 
 def check_admissible(solver, u, what):
@@ -205,8 +257,54 @@ def gpu_steps(solver, u0, nsteps):
     return pipe.state.double().cpu().numpy()
 
 
+def kernel_report(workload, kt, ndof, M, dim, N, stages, flux, precision, ms_step):
+    """Roofline figures of a single-mesh workload from the live kernel times
+    kt (timed()): the dominant kernel is the local phase's instance without
+    the blending code.  Bytes and FLOPs are algorithmic (per DOF x DOFs per
+    launch) over that kernel's average duration; counter figures come from
+    the profile summary taken with the same kernel sources (else null)."""
+    elem = 8 if precision == "fp64" else 4
+    # the instance that did the work: without tile flags (Ranocha, or no
+    # limiter) one of the two launches is empty
+    plain = kt["k_local_plain_ms"] >= kt["k_local_blend_ms"]
+    t_ms = kt["k_local_plain_ms"] if plain else kt["k_local_blend_ms"]
+    t = t_ms * 1e-3
+    kb = k2_bytes_per_dof(M, dim, N, elem) * ndof
+    db = k2_design_bytes_per_dof(M, dim, N, elem) * ndof
+    sb = step_bytes_per_dof(M, dim, N, elem) * ndof
+    ff = k2_formula_flops_per_dof(flux, N, dim, stages, M) * ndof
+    peak_f = PEAK_FP64_TFLOPS if precision == "fp64" else PEAK_FP32_TFLOPS
+    r = {"bound": "hbm",
+         "kernel": "k_local (local stages, instance " + ("without" if plain else "with") + " the blending code)",
+         "achieved": kb / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": kb / t / 1e9 / PEAK_HBM_GBS,
+         "traffic": None, "kernel_ms": t_ms,
+         "algorithmic_bytes_per_dof": kb / ndof, "algorithmic_bytes_per_launch": kb,
+         # this library's own traces (flux shares instead of U, F and u^n)
+         "design_bytes_per_dof": db / ndof, "design_frac": db / t / 1e9 / PEAK_HBM_GBS,
+         "local_phase_ms": kt["local_phase_ms"],
+         "other_instance_ms": kt["k_local_blend_ms"] if plain else kt["k_local_plain_ms"],
+         "interface_ms": kt["interface_ms"],
+         # the whole step against its own algorithmic bytes
+         "step_bytes_per_dof": sb / ndof, "step_achieved_gbs": sb / (ms_step * 1e-3) / 1e9,
+         "step_frac": sb / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS,
+         "formula_flops_per_dof": ff / ndof, "formula_tflops": ff / t / 1e12, "vector_peak_tflops": peak_f,
+         "formula_frac": ff / t / 1e12 / peak_f,
+         "counter_tflops": None, "counter_frac": None, "counter_profile": None}
+    rec = profiled_counters(workload)
+    if rec is not None and rec.get("kernel_instance") != ("plain" if plain else "blend"):
+        rec = None
+    if rec is not None:
+        r["traffic"] = rec["hbm_bytes"]
+        fl = rec.get("fp64_flops" if precision == "fp64" else "fp32_flops")
+        if fl is not None:
+            r["counter_tflops"] = fl / t / 1e12
+            r["counter_frac"] = r["counter_tflops"] / peak_f
+        r["counter_profile"] = rec["profile"]
+    return r
+
+
 def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, threads, learned=False, flux=None,
-                rough=0.0, half=False):
+                rough=0.0, half=False, workload=None):
     import numpy as np
     cfg = dict(KHI)
     if flux is not None:
@@ -229,19 +327,18 @@ def variant_khi(crk, inputs, orc, n, precision, steps, warmup, err_steps, thread
         return u
     u0 = start(xi)
     pipe = Pipelined(s, u0)
-    el, k2_ms = timed(pipe, steps, warmup, events=True)
+    el, kt = timed(pipe, steps, warmup, events=True)
     check_admissible(s, pipe.state, f"khi{n}")
     cons = conservation(pipe)
-    ndof = s.nelem * s.shape[2]
+    M, E, NP = s.shape
+    ndof = E * NP
+    prec = "fp64" if precision == crk.FP64 else "fp32"
     out = {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
-           "k_local_ms": k2_ms}
+           "kernels_ms": kt}
+    if workload is not None:
+        out["roofline"] = kernel_report(workload, kt, ndof, M, 2, 3, 4, cfg["volume_flux"], prec, el / steps * 1e3)
     out["conservation"] = cons
     out["blended_element_fraction"] = float((s.indicator(pipe.state)[1] > 0).double().mean().item())
-    key = (f"khi{n}" + ("_ranocha" if flux == crk.VOL_RANOCHA else ""), "fp64" if precision == crk.FP64 else "fp32")
-    rec = MEASURED_TRAFFIC.get(key)
-    if rec and rec["sources_sha256"] == sources_digest() and flux is not None:
-        out["k_local_fp64_tflops"] = rec["fp64_flops"] / (k2_ms * 1e-3) / 1e12
-        out["k_local_fp64_frac"] = out["k_local_fp64_tflops"] / PEAK_FP64_TFLOPS
     if err_steps:
         p = orc.Problem(dim=2, nx=n, ny=n, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3,
                         vol_flux=orc.VOL_KG if flux is None else flux, limiter=orc.LIM_BLEND_MODAL, nthreads=threads)
@@ -319,15 +416,21 @@ def variant_mhd(crk, inputs, orc, precision, steps, warmup, threads):
     xi, _, _ = crk.reference_element(4)
     u0 = inputs.orszag_tang(n, n, xi)
     pipe = Pipelined(s, u0)
-    el, _ = timed(pipe, steps, warmup)
+    el, kt = timed(pipe, steps, warmup, events=True)
     check_admissible(s, pipe.state, "mhd")
     cons = conservation(pipe)
     p = orc.Problem(dim=2, nx=n, ny=n, N=4, eq=orc.MHD, gamma=5.0 / 3.0, vol_flux=orc.VOL_DERIGS, nthreads=threads)
     oxi, _ = orc.gll(4)
     ref = oracle_steps(p, inputs.orszag_tang(n, n, oxi), 1)
     got1 = gpu_steps(s, u0, 1)
-    ndof = s.nelem * s.shape[2]
+    M, E, NP = s.shape
+    ndof = E * NP
+    prec = "fp64" if precision == crk.FP64 else "fp32"
+    rl = kernel_report(f"mhd_ot192_{prec}", kt, ndof, M, 2, 4, 6, crk.VOL_DERIGS, prec, el / steps * 1e3)
+    # by the formula counts this kernel is balanced between FP64 issue and HBM
+    rl["bound"] = "balanced (vector FLOPs and HBM)"
     return {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
+            "kernels_ms": kt, "roofline": rl,
             "l2_rel_error_vs_fp64_oracle": rel_l2(got1, ref), "linf_rel_error_vs_fp64_oracle": rel_linf(got1, ref),
             "error_after_steps": 1, "conservation": cons}
 
@@ -363,6 +466,44 @@ def variant_wave1d(crk, inputs, orc):
             "max_velocity_deviation": float(np.max(np.abs(got[1] / got[0] - 0.1)))}
 
 
+def host_cpu():
+    """Host CPU model and the logical CPU count of the machine."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(orc, inputs, threads, steps_all, steps_one):
+    """The FP64 CPU oracle on the headline workload (KHI 256^2), timed on the
+    host: `steps_all` full steps with OpenMP over elements on `threads`
+    threads, and `steps_one` steps on one thread."""
+    oxi, _ = orc.gll(3)
+    u0 = inputs.kelvin_helmholtz(256, 256, oxi)
+    ndof = 256 * 256 * 16
+    rates = {}
+    for nth, nsteps in ((threads, steps_all), (1, steps_one)):
+        p = orc.Problem(dim=2, nx=256, ny=256, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=orc.VOL_KG,
+                        limiter=orc.LIM_BLEND_MODAL, nthreads=nth)
+        uc = u0
+        c0 = time.perf_counter()
+        for _ in range(nsteps):
+            uc, _ = orc.crk_step(p, uc, orc.compute_dt(p, uc))
+        rates[nth] = ndof * nsteps / (time.perf_counter() - c0)
+    model, ncpu = host_cpu()
+    return {"value": rates[threads], "unit": "DOF-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps_all} full steps of the headline workload (KHI 256x256, N=3, KG, blending; FP64 C "
+                      f"oracle, OpenMP over elements on {threads} threads) and {steps_one} steps on one thread",
+            "single_thread_value": rates[1], "host_cpu_model": model, "host_logical_cpus": ncpu,
+            "threads_note": "threads = the host CPU share of one GPU (OMP_NUM_THREADS on the GPU host)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -370,10 +511,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    # the blended variant launches the headline's local-stage kernel on the same
-    # grid: profiler runs skip it so that per-kernel averages cover the headline
+    # the blended variants launch the headline's local-stage kernels on the same
+    # grid: profiler runs skip them so that per-kernel averages cover the headline
     ap.add_argument("--no-blended", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--only", default=None, help="comma-separated variant names to run (profiling)")
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps-single", type=int, default=2)
     ap.add_argument("--err-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (HBM counter calibration)")
@@ -394,26 +537,15 @@ def main():
         print(json.dumps({"copy_bytes_each_way": n * 8, "copies": 5}))
         return
 
+    import oracle as orc
     from paper_2604_02125_amd import crk, inputs
     torch.cuda.set_device(0)
-    threads = min(16, os.cpu_count() or 1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
 
     # ------------------------------------------------------------ headline
-    s = crk.Solver(nx=256, ny=256, precision=crk.FP64, **KHI)
-    xi, _, _ = crk.reference_element(3)
-    u0 = inputs.kelvin_helmholtz(256, 256, xi)
-    M, E, NP = s.shape
-    ndof = E * NP
-    pipe = Pipelined(s, u0)
-    elapsed, k2_ms = timed(pipe, args.steps, args.warmup, events=True)
-    check_admissible(s, pipe.state, "the timed steps")
-    value = ndof * args.steps / elapsed
-    kb = k2_bytes_per_dof(M, 2, 3, 8) * ndof
-    achieved = kb / (k2_ms * 1e-3) / 1e9
-    rec = MEASURED_TRAFFIC.get(("khi256", "fp64"))
-    fresh = bool(rec) and rec["sources_sha256"] == sources_digest()
-    traffic = rec["bytes"] if fresh else None
-    fp64 = rec["fp64_flops"] / (k2_ms * 1e-3) / 1e12 if fresh else None
+    head = variant_khi(crk, inputs, orc, 256, crk.FP64, args.steps, args.warmup, 0, threads,
+                       workload="khi256_fp64")
+    value = head["value"]
     out = {
         "metric": "DOF-updates/s at 1 GPU",
         "value": value,
@@ -421,60 +553,62 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (analytic Kelvin-Helmholtz initial condition)",
         "config": {"workload": "2D Euler Kelvin-Helmholtz 256x256, N=3, Kennedy-Gruber, blending alpha_max=0.008",
-                   "elements": E, "degree": 3, "dofs": ndof, "precision": "fp64", "parallelism": "single GPU"},
+                   "elements": 65536, "degree": 3, "dofs": 1048576, "precision": "fp64",
+                   "parallelism": "single GPU"},
         # a DOF is a node; the same rate counted per conserved variable (x M = 4)
         "variable_dof_updates_per_s": value * 4,
-        "roofline": {"bound": "hbm", "kernel": "k_local (local stages)", "achieved": achieved,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic, "kernel_ms": k2_ms, "algorithmic_bytes_per_launch": kb,
-                     # counter FP64 FLOPs of the same kernel over its live duration
-                     "fp64_tflops": fp64, "fp64_peak_tflops": PEAK_FP64_TFLOPS,
-                     "fp64_frac": fp64 / PEAK_FP64_TFLOPS if fp64 is not None else None},
+        "roofline": head["roofline"],
+        "kernels_ms": head["kernels_ms"],
+        "conservation": head["conservation"],
+        "blended_element_fraction": head["blended_element_fraction"],
     }
-    import oracle as orc
     if not args.no_cpu_baseline:
-        p = orc.Problem(dim=2, nx=256, ny=256, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=orc.VOL_KG,
-                        limiter=orc.LIM_BLEND_MODAL, nthreads=threads)
-        oxi, _ = orc.gll(3)
-        uc = inputs.kelvin_helmholtz(256, 256, oxi)
-        c0 = time.perf_counter()
-        for _ in range(args.cpu_steps):
-            uc, _ = orc.crk_step(p, uc, orc.compute_dt(p, uc))
-        c1 = time.perf_counter()
-        out["cpu_baseline"] = {"value": ndof * args.cpu_steps / (c1 - c0), "unit": "DOF-updates/s",
-                               "cores": threads, "kind": "oracle",
-                               "sample": f"{args.cpu_steps} full steps of the same workload (FP64 C oracle, "
-                                         f"OpenMP over elements, {threads} threads)"}
+        out["cpu_baseline"] = cpu_baseline(orc, inputs, threads, args.cpu_steps, args.cpu_steps_single)
     if not args.no_variants:
+        only = set(args.only.split(",")) if args.only else None
+        want = lambda k: only is None or k in only
         v = {}
-        v["khi256_fp64"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps, threads)
-        v["khi256_fp32"] = variant_khi(crk, inputs, orc, 256, crk.FP32, 20, 2, args.err_steps, threads)
-        # the same workload with the entropy-conservative Ranocha flux (log means)
-        v["khi256_ranocha_fp64"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps, threads,
-                                               flux=crk.VOL_RANOCHA)
+        if want("khi256_fp64_check"):
+            v["khi256_fp64_check"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps, threads)
+        if want("khi256_fp32"):
+            v["khi256_fp32"] = variant_khi(crk, inputs, orc, 256, crk.FP32, 20, 2, args.err_steps, threads,
+                                           workload="khi256_fp32")
+        if want("khi256_ranocha_fp64"):
+            # the same workload with the entropy-conservative Ranocha flux (log means)
+            v["khi256_ranocha_fp64"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps, threads,
+                                                   flux=crk.VOL_RANOCHA, workload="khi256_ranocha_fp64")
         if not args.no_blended:
-            v["khi256_blended_fp64"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps,
-                                                   threads, rough=0.05)
-            v["khi256_half_blended_fp64"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps,
-                                                        threads, rough=0.05, half=True)
-        v["batch512_fp64"] = variant_batch(crk, inputs, orc, crk.FP64, 5)
-        v["batch512_fp32"] = variant_batch(crk, inputs, orc, crk.FP32, 5)
-        v["khi512_learned_fp64"] = variant_khi(crk, inputs, orc, 512, crk.FP64, 10, 2, args.err_steps, threads,
-                                               learned=True)
-        v["mhd_ot192_fp64"] = variant_mhd(crk, inputs, orc, crk.FP64, 10, 2, threads)
-        v["mhd_ot192_fp32"] = variant_mhd(crk, inputs, orc, crk.FP32, 10, 2, threads)
-        v["density_wave_1d_fp64"] = variant_wave1d(crk, inputs, orc)
+            if want("khi256_blended_fp64"):
+                v["khi256_blended_fp64"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps,
+                                                       threads, rough=0.05)
+            if want("khi256_half_blended_fp64"):
+                v["khi256_half_blended_fp64"] = variant_khi(crk, inputs, orc, 256, crk.FP64, 20, 2, args.err_steps,
+                                                            threads, rough=0.05, half=True)
+        if want("batch512_fp64"):
+            v["batch512_fp64"] = variant_batch(crk, inputs, orc, crk.FP64, 5)
+        if want("batch512_fp32"):
+            v["batch512_fp32"] = variant_batch(crk, inputs, orc, crk.FP32, 5)
+        if want("khi512_learned_fp64"):
+            v["khi512_learned_fp64"] = variant_khi(crk, inputs, orc, 512, crk.FP64, 10, 2, args.err_steps, threads,
+                                                   learned=True)
+        if want("mhd_ot192_fp64"):
+            v["mhd_ot192_fp64"] = variant_mhd(crk, inputs, orc, crk.FP64, 10, 2, threads)
+        if want("mhd_ot192_fp32"):
+            v["mhd_ot192_fp32"] = variant_mhd(crk, inputs, orc, crk.FP32, 10, 2, threads)
+        if want("density_wave_1d_fp64"):
+            v["density_wave_1d_fp64"] = variant_wave1d(crk, inputs, orc)
         v["_note"] = ("l2_rel_error_vs_fp64_oracle = ||u_gpu - u_oracle||_2 / ||u_oracle||_2 and "
                       "linf_rel_error_vs_fp64_oracle = max|u_gpu - u_oracle| / max|u_oracle| over all values "
                       "after error_after_steps steps from the same initial state (the FP64 rows are a "
-                      "round-off check)")
+                      "round-off check); roofline.achieved = algorithmic bytes per launch / the dominant "
+                      "kernel's live duration (HIP events)")
         out["variants"] = v
     print(json.dumps(out))
 
