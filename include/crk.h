@@ -170,6 +170,25 @@ crk_status crk_indicator(crk_solver *s, const void *u, double *alpha_raw, double
 crk_status crk_fr_rhs(crk_solver *s, const void *u, const double *dt_dev, int surface, void *rhs,
                       crk_stream stream);
 
+#define CRK_STEP_COMPUTE_DT 1   /* flag of crk_step and crk_rkfr_step: compute dt first */
+
+/* Standard s-stage RKFR step of eq:rkfr.non.cons, the scheme cRKFR is
+ * compared with: every stage applies the semi-discrete operator of
+ * crk_fr_rhs (the solver's volume flux, Rusanov faces with lambda from both
+ * stage traces, MHD: 1/2 B(u)(g^- + g^+) at the faces) to the stage state,
+ * so a step needs s interface exchanges instead of one:
+ *   K_i = L(u^(i)), u^(i) = u_in + dt sum_{m<i} a_im K_m,
+ *   u_out = u_in + dt sum_i b_i K_i.
+ * flags & CRK_STEP_COMPUTE_DT: dt_dev from u_in first (needs the solver's
+ * workspace), else dt_dev is an input ([dt, c_h]; c_h is held fixed over
+ * the step).  rk_ws: caller-owned device scratch of crk_rkfr_workspace_bytes
+ * (two stage states and the s stage derivatives).  No limiter
+ * (CRK_ERR_UNSUPPORTED when the solver has one).  u_in, u_out distinct, not
+ * in rk_ws, 256-byte aligned; stream-ordered. */
+crk_status crk_rkfr_workspace_bytes(const crk_solver *s, size_t *bytes);
+crk_status crk_rkfr_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, int flags, void *rk_ws,
+                         size_t rk_ws_bytes, crk_stream stream);
+
 /* Local phase (eq:crkfr.inner, eq:disc.avg.flux, Section 3 volume terms):
  * for every element the s inner stages with flux differencing, then
  *   u_out = u_in - dt [(1-alpha_e) V + alpha_e L]   (V = sum_j b_j R^(j);
@@ -202,7 +221,6 @@ crk_status crk_interface_update(crk_solver *s, const void *u_in, const void *tra
  * workspace; u_in and u_out must not alias.  Uses the workspace state of
  * the pipelined calls below: after crk_step, crk_advance needs crk_prepare
  * again (CRK_ERR_STATE otherwise). */
-#define CRK_STEP_COMPUTE_DT 1
 crk_status crk_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, const double *alpha_in,
                     int flags, crk_stream stream);
 

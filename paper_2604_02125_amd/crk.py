@@ -80,6 +80,8 @@ def lib():
             "crk_step": (st, [_vp, _vp, _vp, _vp, _vp, C.c_int, _vp]),
             "crk_diagnostics": (st, [_vp, _vp, _vp, _vp]),
             "crk_check": (st, [_vp, _vp, C.POINTER(C.c_int64), _dp, _vp]),
+            "crk_rkfr_workspace_bytes": (st, [_vp, C.POINTER(C.c_size_t)]),
+            "crk_rkfr_step": (st, [_vp, _vp, _vp, _vp, C.c_int, _vp, C.c_size_t, _vp]),
             "crk_prepare": (st, [_vp, _vp, _vp, _vp]),
             "crk_advance": (st, [_vp, _vp, _vp, _vp, C.c_int, _vp]),
             "crk_last_error": (C.c_char_p, []),
@@ -224,6 +226,19 @@ class Solver:
         self._check_state(u_out)
         _check(lib().crk_step(self._h, _ptr(u_in), _ptr(u_out), _ptr(dt), _ptr(alpha),
                               STEP_COMPUTE_DT if compute_dt else 0, _stream(stream)), "crk_step")
+
+    def rkfr_step(self, u_in, u_out, dt, compute_dt=True, stream=None):
+        """One standard s-stage RKFR step (s interface exchanges); the stage
+        scratch is allocated on first use and kept."""
+        import torch
+        self._check_state(u_in)
+        self._check_state(u_out)
+        if getattr(self, "_rk_ws", None) is None:
+            nb = C.c_size_t()
+            _check(lib().crk_rkfr_workspace_bytes(self._h, C.byref(nb)), "crk_rkfr_workspace_bytes")
+            self._rk_ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        _check(lib().crk_rkfr_step(self._h, _ptr(u_in), _ptr(u_out), _ptr(dt), STEP_COMPUTE_DT if compute_dt else 0,
+                                   _ptr(self._rk_ws), self._rk_ws.numel(), _stream(stream)), "crk_rkfr_step")
 
     def prepare(self, u, dt, stream=None):
         self._check_state(u)

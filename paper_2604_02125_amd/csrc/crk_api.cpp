@@ -419,6 +419,45 @@ crk_status crk_fr_rhs(crk_solver *s, const void *u, const double *dt_dev, int su
     return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_fr_rhs");
 }
 
+crk_status crk_rkfr_workspace_bytes(const crk_solver *s, size_t *bytes)
+{
+    if (!s || !bytes) return fail(CRK_ERR_ARG, "null argument");
+    *bytes = (size_t)(s->t.stages + 2) * align256(s->state_bytes);
+    return CRK_OK;
+}
+
+crk_status crk_rkfr_step(crk_solver *s, const void *u_in, void *u_out, double *dt_dev, int flags, void *rk_ws,
+                         size_t rk_ws_bytes, crk_stream stream)
+{
+    if (!s || !u_in || !u_out || !dt_dev || !rk_ws) return fail(CRK_ERR_ARG, "null argument");
+    if (u_in == u_out) return fail(CRK_ERR_ARG, "u_in and u_out must not alias");
+    if (!is_aligned(u_in) || !is_aligned(u_out) || !is_aligned(rk_ws))
+        return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
+    if (flags & ~CRK_STEP_COMPUTE_DT) return fail(CRK_ERR_ARG, "unknown flag bits");
+    if (s->limiter != CRK_LIM_NONE) return fail(CRK_ERR_UNSUPPORTED, "the standard RKFR step has no limiter");
+    size_t need = 0;
+    crk_rkfr_workspace_bytes(s, &need);
+    if (rk_ws_bytes < need) return fail(CRK_ERR_ARG, "RKFR workspace too small (crk_rkfr_workspace_bytes)");
+    char *w = (char *)rk_ws;
+    const char *ui = (const char *)u_in, *uo = (const char *)u_out;
+    if ((uo + s->state_bytes > w && uo < w + need) || (ui + s->state_bytes > w && ui < w + need))
+        return fail(CRK_ERR_ARG, "u_in or u_out overlaps the RKFR workspace");
+    if (flags & CRK_STEP_COMPUTE_DT) {
+        crk_status st = crk_compute_dt(s, u_in, dt_dev, stream);
+        if (st) return st;
+    }
+    const size_t sb = align256(s->state_bytes);
+    RkPtrs p{};
+    p.u_n = u_in;
+    p.k = w + 2 * sb;
+    p.dt = dt_dev;
+    // the K arrays are packed at the state's own size (the kernel indexes them by m * nvar * nodes)
+    hipError_t e = dispatch(s, [&](auto fam) {
+        return decltype(fam)::rkfr(s->t, s->flux, p, w, w + sb, u_out, (hipStream_t)stream);
+    });
+    return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_rkfr_step");
+}
+
 crk_status crk_indicator(crk_solver *s, const void *u, double *alpha_raw, double *alpha, crk_stream stream)
 {
     if (!s || !u) return fail(CRK_ERR_ARG, "null argument");

@@ -21,6 +21,9 @@ struct Family {
     // semi-discrete FR operator du/dt of u into rhs (test operator, crk_rhs.hpp)
     static hipError_t fr_rhs(const Tables &t, int flux, const void *u, const double *dtc, int surface, void *rhs,
                              hipStream_t s);
+    // the s stages of a standard RKFR step (crk_rhs.hpp); stage states in b0, b1
+    static hipError_t rkfr(const Tables &t, int flux, const RkPtrs &p, void *b0, void *b1, void *u_out,
+                           hipStream_t s);
 };
 
 // fluxes compiled for an equation system

@@ -61,6 +61,29 @@ hipError_t Family<real, EQ, DIM>::fr_rhs(const Tables &t, int flux, const void *
 }
 
 template <typename real, int EQ, int DIM>
+hipError_t Family<real, EQ, DIM>::rkfr(const Tables &t, int flux, const RkPtrs &p, void *b0, void *b1, void *uo,
+                                       hipStream_t s)
+{
+#define CRK_RKFR_FLUX(NN)                                                                                       \
+    switch (flux) {                                                                                             \
+    case VOL_CENTRAL: return launch_rkfr<real, EQ, DIM, NN, VOL_CENTRAL>(t, p, b0, b1, uo, s);                 \
+    case VOL_KG: if constexpr (EQ == EQ_EULER) return launch_rkfr<real, EQ, DIM, NN, VOL_KG>(t, p, b0, b1, uo, s); break;           \
+    case VOL_RANOCHA: if constexpr (EQ == EQ_EULER) return launch_rkfr<real, EQ, DIM, NN, VOL_RANOCHA>(t, p, b0, b1, uo, s); break; \
+    case VOL_DERIGS: if constexpr (EQ == EQ_MHD) return launch_rkfr<real, EQ, DIM, NN, VOL_DERIGS>(t, p, b0, b1, uo, s); break;     \
+    default: break;                                                                                             \
+    }                                                                                                           \
+    return hipErrorInvalidValue;
+    switch (t.N) {
+    case 1: { CRK_RKFR_FLUX(1) }
+    case 2: { CRK_RKFR_FLUX(2) }
+    case 3: { CRK_RKFR_FLUX(3) }
+    case 4: { CRK_RKFR_FLUX(4) }
+    default: return hipErrorInvalidValue;
+    }
+#undef CRK_RKFR_FLUX
+}
+
+template <typename real, int EQ, int DIM>
 hipError_t Family<real, EQ, DIM>::face_speed(const Tables &t, int flux, const StepPtrs &p, hipStream_t s)
 {
     CRK_DEGREE_SWITCH(launch_face_speed)

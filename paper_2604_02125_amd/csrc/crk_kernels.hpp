@@ -123,6 +123,15 @@ struct StepPtrs {
     int instances;
 };
 
+// Pointers of one stage of the standard multi-stage RKFR step (crk_rhs.hpp).
+struct RkPtrs {
+    const void *u_n;    // u^n
+    const void *x_in;   // u^(i) (u^n for i = 0)
+    void *x_out;        // u^(i+1), or u^{n+1} after the last stage
+    void *k;            // K_0 .. K_{s-1}, each a state array
+    const double *dt;   // [dt, c_h]
+};
+
 // ---------------------------------------------------------------- helpers
 // element coordinates and the four (two in 1D) face neighbours; e < 2^31.
 // The row index comes from a double-precision product with 1/nx (off by at

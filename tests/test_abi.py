@@ -140,3 +140,28 @@ def test_fr_rhs_validation():
             assert L.crk_fr_rhs(h, u, None, 0, r, None) == -1              # MHD needs c_h
             assert "c_h" in L.crk_last_error().decode()
         L.crk_destroy(h)
+
+
+def test_rkfr_validation():
+    """The standard RKFR step: scratch size, and argument checks before any launch."""
+    L = crk.lib()
+    m = crk.MeshDesc(2, 4, 4, 0.0, 1.0, 0.0, 1.0, 3, crk.CRK_EULER, 1.4, crk.FP64)
+    sc = crk.SchemeDesc()
+    sc.volume_flux, sc.cfl = crk.VOL_KG, 0.4
+    h = C.c_void_p()
+    assert L.crk_create(C.byref(m), C.byref(sc), C.byref(h)) == 0
+    nb = C.c_size_t()
+    assert L.crk_rkfr_workspace_bytes(h, C.byref(nb)) == 0
+    state = 4 * 16 * 16 * 8
+    assert nb.value == (4 + 2) * ((state + 255) // 256 * 256)        # RK4: two stage states + four K
+    u, o, dt, ws = (C.c_void_p(x << 20) for x in (1, 2, 3, 8))
+    assert L.crk_rkfr_step(h, u, u, dt, 0, ws, nb.value, None) == crk.ERR_ARG           # aliasing
+    assert L.crk_rkfr_step(h, u, o, dt, 0, ws, nb.value - 1, None) == crk.ERR_ARG       # scratch too small
+    assert L.crk_rkfr_step(h, u, C.c_void_p((8 << 20) + 256), dt, 0, ws, nb.value, None) == crk.ERR_ARG
+    assert L.crk_rkfr_step(h, u, o, dt, 0, C.c_void_p((8 << 20) + 8), nb.value, None) == crk.ERR_ARG
+    assert L.crk_rkfr_step(h, u, o, None, 0, ws, nb.value, None) == crk.ERR_ARG
+    L.crk_destroy(h)
+    sc.limiter = crk.LIM_BLEND
+    assert L.crk_create(C.byref(m), C.byref(sc), C.byref(h)) == 0
+    assert L.crk_rkfr_step(h, u, o, dt, 0, ws, nb.value, None) == crk.ERR_UNSUPPORTED
+    L.crk_destroy(h)
