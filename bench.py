@@ -466,6 +466,77 @@ def variant_wave1d(crk, inputs, orc):
             "max_velocity_deviation": float(np.max(np.abs(got[1] / got[0] - 0.1)))}
 
 
+def variant_rkfr(crk, inputs, orc, steps, warmup, threads, err=True):
+    """cRKFR against the standard multi-stage RKFR step on the same mesh,
+    fluxes and tableau (KHI 256^2, N=3, Kennedy-Gruber, RK4, no limiter):
+    one interface exchange per step against one per stage."""
+    import numpy as np
+    import torch
+    n = 256
+    cfg = dict(KHI)
+    cfg["limiter"] = 0
+    s = crk.Solver(nx=n, ny=n, precision=crk.FP64, **cfg)
+    xi, _, _ = crk.reference_element(3)
+    u0 = inputs.kelvin_helmholtz(n, n, xi)
+    M, E, NP = s.shape
+    ndof = E * NP
+    pipe = Pipelined(s, u0)
+    el_c, kt = timed(pipe, steps, warmup, events=True)
+    # RKFR: dt of the state, then the s stages, every step
+    ug = torch.tensor(u0, device="cuda")
+    buf, dt = [ug.clone(), s.new_state()], s.new_dt()
+    for k in range(warmup):
+        s.rkfr_step(buf[k % 2], buf[(k + 1) % 2], dt, compute_dt=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        s.rkfr_step(buf[(warmup + k) % 2], buf[(warmup + k + 1) % 2], dt, compute_dt=True)
+    torch.cuda.synchronize()
+    el_r = time.perf_counter() - t0
+    check_admissible(s, buf[(warmup + steps) % 2], "rkfr")
+    S = 4
+    out = {"workload": "2D Euler Kelvin-Helmholtz 256x256, N=3, Kennedy-Gruber, RK4, Rusanov faces, no limiter, FP64",
+           "crkfr": {"value": ndof * steps / el_c, "ms_per_step": el_c / steps * 1e3, "interface_exchanges_per_step": 1,
+                     "algorithmic_bytes_per_dof": step_bytes_per_dof(M, 2, 3, 8), "kernels_ms": kt},
+           "rkfr": {"value": ndof * steps / el_r, "ms_per_step": el_r / steps * 1e3, "interface_exchanges_per_step": S,
+                    # per stage: stage state in, u^n in, next stage state and K_i out; last stage:
+                    # stage state, u^n and K_0..K_2 in, u^{n+1} out; plus the dt pass over u^n
+                    "algorithmic_bytes_per_dof": 8.0 * M * (4 * (S - 1) + (2 + S) + 1)},
+           "steps": steps}
+    out["crkfr_over_rkfr"] = out["crkfr"]["value"] / out["rkfr"]["value"]
+    if err:
+        p = orc.Problem(dim=2, nx=n, ny=n, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=orc.VOL_KG,
+                        nthreads=threads)
+        oxi, _ = orc.gll(3)
+        uo = inputs.kelvin_helmholtz(n, n, oxi)
+        dto = orc.compute_dt(p, uo)
+        ref = orc.rkfr_step(p, uo, dto)
+        o1 = s.new_state()
+        s.rkfr_step(ug, o1, torch.tensor([dto, 0.0], dtype=torch.float64, device="cuda"), compute_dt=False)
+        got = o1.cpu().numpy()
+        out["rkfr"]["l2_rel_error_vs_fp64_oracle"] = rel_l2(got, ref)
+        out["rkfr"]["linf_rel_error_vs_fp64_oracle"] = rel_linf(got, ref)
+        # one step of each scheme from the same state and dt: how far the
+        # single-exchange scheme lands from the s-exchange one
+        ref_c, _ = orc.crk_step(p, uo, dto)
+        out["crkfr_vs_rkfr_one_step_rel_l2"] = rel_l2(ref_c, ref)
+    return out
+
+
+def variant_crash_study(crk):
+    """Section 4.2's robustness claim on the paper's own mesh: KHI 64^2, N=3,
+    blending with alpha_max = 0.008, to t = 15, for the central (plain FR
+    derivative), Kennedy-Gruber and Ranocha volume fluxes."""
+    from paper_2604_02125_amd import robustness
+    t0 = time.perf_counter()
+    res = robustness.khi_crash_study()
+    return {"workload": "2D Euler Kelvin-Helmholtz 64x64, N=3, rho = 1/4 + 3B/4, blending alpha_max=0.008, "
+                        "CFL 0.4, to t=15",
+            "runs": res, "wall_s": time.perf_counter() - t0,
+            "paper_context": "paper (Section 4.2, unstated hardware): stable to t=15 with the EC or KEP flux, "
+                             "crash at about t=4 without"}
+
+
 def host_cpu():
     """Host CPU model and the logical CPU count of the machine."""
     model = None
@@ -604,6 +675,10 @@ def main():
             v["mhd_ot192_fp32"] = variant_mhd(crk, inputs, orc, crk.FP32, 10, 2, threads)
         if want("density_wave_1d_fp64"):
             v["density_wave_1d_fp64"] = variant_wave1d(crk, inputs, orc)
+        if want("khi256_crkfr_vs_rkfr"):
+            v["khi256_crkfr_vs_rkfr"] = variant_rkfr(crk, inputs, orc, 20, 2, threads, err=args.err_steps > 0)
+        if want("khi64_crash_study"):
+            v["khi64_crash_study"] = variant_crash_study(crk)
         v["_note"] = ("l2_rel_error_vs_fp64_oracle = ||u_gpu - u_oracle||_2 / ||u_oracle||_2 and "
                       "linf_rel_error_vs_fp64_oracle = max|u_gpu - u_oracle| / max|u_oracle| over all values "
                       "after error_after_steps steps from the same initial state (the FP64 rows are a "
