@@ -32,6 +32,7 @@ EULER, MHD = 0, 1
 VOL_CENTRAL, VOL_KG, VOL_RANOCHA, VOL_DERIGS = 0, 1, 2, 3
 LIM_NONE, LIM_BLEND_MODAL, LIM_BLEND_GIVEN = 0, 1, 2
 SURF_RUSANOV, SURF_EC = 0, 1
+BC_PERIODIC, BC_WALL = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -51,7 +52,7 @@ class _Problem(C.Structure):
                 ("A", C.c_double * (MAXS * MAXS)), ("b", C.c_double * MAXS),
                 ("vol_flux", C.c_int), ("limiter", C.c_int),
                 ("alpha_max", C.c_double), ("alpha_min", C.c_double), ("cfl", C.c_double),
-                ("ch", C.c_double), ("nthreads", C.c_int)]
+                ("ch", C.c_double), ("nthreads", C.c_int), ("bc", C.c_int * 2), ("nc_stagewise", C.c_int)]
 
 
 # Butcher tableaus (eq:butcher).  The paper does not list the tableau it uses
@@ -95,6 +96,8 @@ class Problem:
     cfl: float = 0.4
     ch: float = 0.0
     nthreads: int = 1
+    bc: tuple = (BC_PERIODIC, BC_PERIODIC)   # per direction: periodic or reflective wall
+    nc_stagewise: int = 0                    # MHD interface flux: 0 reduced form, 1 stage-wise
 
     def __post_init__(self):
         if self.A is None or self.b is None:
@@ -118,8 +121,9 @@ class Problem:
 
     def to_c(self) -> _Problem:
         p = _Problem()
-        for k in ("dim", "nx", "ny", "N", "eq", "vol_flux", "limiter", "nthreads"):
+        for k in ("dim", "nx", "ny", "N", "eq", "vol_flux", "limiter", "nthreads", "nc_stagewise"):
             setattr(p, k, int(getattr(self, k)))
+        p.bc[0], p.bc[1] = int(self.bc[0]), int(self.bc[1])
         for k in ("x0", "x1", "y0", "y1", "gamma", "alpha_max", "alpha_min", "cfl", "ch"):
             setattr(p, k, float(getattr(self, k)))
         s = len(self.b)
@@ -335,7 +339,8 @@ def face_fluxes(prob: Problem, u, dt: float, alpha=None):
 def fr_rhs(prob: Problem, u, surface: int = SURF_RUSANOV):
     u = _f64(u)
     r = np.empty_like(u)
-    lib().orc_fr_rhs(C.byref(prob.to_c()), _ptr(u), int(surface), _ptr(r))
+    if lib().orc_fr_rhs(C.byref(prob.to_c()), _ptr(u), int(surface), _ptr(r)) != 0:
+        raise ValueError("orc_fr_rhs: unsupported configuration")
     return r
 
 

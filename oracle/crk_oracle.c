@@ -53,7 +53,11 @@ typedef struct {
     double cfl;
     double ch;                        /* GLM cleaning speed (MHD), fixed per step */
     int nthreads;
+    int bc[2];                        /* per direction: ORC_BC_PERIODIC or ORC_BC_WALL */
+    int nc_stagewise;                 /* MHD interface flux: 0 reduced form, 1 stage-wise */
 } orc_problem;
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_WALL = 1 };
 
 /* ------------------------------------------------------------------ */
 /* Small helpers                                                        */
@@ -462,6 +466,33 @@ static long neighbour(const orc_problem *P, long e, int d, int side)
     return ey * P->nx + ex;
 }
 
+/* Reflective (slip) walls: a face of direction d on the boundary of the
+ * domain (the paper does not state the boundary conditions of its
+ * Richtmyer-Meshkov test; walls are this oracle's reading).  Outside the
+ * wall lies the mirror image of the element: the state with the normal
+ * momentum negated, evolving as the mirror image of the element. */
+static int at_wall(const orc_problem *P, long e, int d, int side)
+{
+    if (P->bc[d] != ORC_BC_WALL) return 0;
+    long ex = P->dim == 1 ? e : e % P->nx, ey = P->dim == 1 ? 0 : e / P->nx;
+    long i = d == 0 ? ex : ey, n = d == 0 ? P->nx : P->ny;
+    return side ? i == n - 1 : i == 0;
+}
+
+/* the face neighbour, or e itself across a wall (its mirror image) */
+static long neighbour_or_self(const orc_problem *P, long e, int d, int side)
+{
+    return at_wall(P, e, d, side) ? e : neighbour(P, e, d, side);
+}
+
+/* mirror image across a wall normal to direction d (Euler): rho v_d -> -rho v_d */
+static void mirror_state(const orc_problem *P, int d, const double *u, double *out)
+{
+    int M = orc_nvar(P);
+    for (int v = 0; v < M; ++v) out[v] = u[v];
+    out[1 + d] = -u[1 + d];
+}
+
 static int nface_nodes(const orc_problem *P) { return P->dim == 2 ? P->N + 1 : 1; }
 
 /* node of face (d, side) with face-node index k */
@@ -630,7 +661,7 @@ int orc_indicator(const orc_problem *P, const double *u, double *alpha_raw, doub
         double a = alpha_raw[e];
         for (int d = 0; d < P->dim; ++d)
             for (int side = 0; side < 2; ++side) {
-                double an = 0.5 * alpha_raw[neighbour(P, e, d, side)];
+                double an = 0.5 * alpha_raw[neighbour_or_self(P, e, d, side)];
                 if (an > a) a = an;
             }
         alpha[e] = a;
@@ -658,12 +689,42 @@ int orc_indicator(const orc_problem *P, const double *u, double *alpha_raw, doub
 /* ------------------------------------------------------------------ */
 typedef struct {
     double *Ut, *Ft, *Fnct;
+    /* at wall faces, the traces of the mirror image beyond the wall:
+     * sum_j b_j R u^(j) and sum_j b_j f_d(R u^(j)) (NULL without walls) */
+    double *UGt, *FGt;
+    /* stage-wise non-conservative interface flux: the stage states u^(j) at
+     * the face nodes, [e][face][k][j][v] (NULL otherwise) */
+    double *Ust;
 } traces_t;
 
 static long tr_index(const orc_problem *P, long e, int face, int k, int v)
 {
     int nf = nface_nodes(P), M = orc_nvar(P);
     return (((e * (2 * P->dim) + face) * nf + k) * M + v);
+}
+
+static long st_index(const orc_problem *P, long e, int face, int k, int j, int v)
+{
+    int nf = nface_nodes(P), M = orc_nvar(P);
+    return ((((e * (2 * P->dim) + face) * nf + k) * P->stages + j) * M + v);
+}
+
+static int has_walls(const orc_problem *P) { return P->bc[0] == ORC_BC_WALL || (P->dim == 2 && P->bc[1] == ORC_BC_WALL); }
+
+static void traces_alloc(const orc_problem *P, traces_t *T)
+{
+    long ntr = nelem_of(P) * 2 * P->dim * nface_nodes(P) * orc_nvar(P);
+    T->Ut = malloc(sizeof(double) * ntr);
+    T->Ft = malloc(sizeof(double) * ntr);
+    T->Fnct = malloc(sizeof(double) * ntr);
+    T->UGt = has_walls(P) ? calloc(ntr, sizeof(double)) : NULL;
+    T->FGt = has_walls(P) ? calloc(ntr, sizeof(double)) : NULL;
+    T->Ust = P->nc_stagewise ? malloc(sizeof(double) * ntr * P->stages) : NULL;
+}
+
+static void traces_free(traces_t *T)
+{
+    free(T->Ut); free(T->Ft); free(T->Fnct); free(T->UGt); free(T->FGt); free(T->Ust);
 }
 
 /* inner stages, time averages and traces of element e; V[node][v] */
@@ -699,7 +760,9 @@ static void local_stages(const orc_problem *P, const refel_t *r, const double *u
                     T->Ut[tr_index(P, e, face, k, v)] = 0.0;
                     T->Ft[tr_index(P, e, face, k, v)] = 0.0;
                     T->Fnct[tr_index(P, e, face, k, v)] = 0.0;
+                    if (T->UGt) T->UGt[tr_index(P, e, face, k, v)] = T->FGt[tr_index(P, e, face, k, v)] = 0.0;
                 }
+                int wall = at_wall(P, e, d, side);
                 for (int j = 0; j < S; ++j) {
                     const double *uj = us + (j * np + p) * M;
                     double f[ORC_MAXM], nc[ORC_MAXM];
@@ -710,6 +773,18 @@ static void local_stages(const orc_problem *P, const refel_t *r, const double *u
                         T->Ft[tr_index(P, e, face, k, v)] += P->b[j] * f[v];
                         T->Fnct[tr_index(P, e, face, k, v)] += P->b[j] * nc[v];
                     }
+                    if (wall) {
+                        /* the mirror image evolves as the mirror of the element */
+                        double um[ORC_MAXM], fm[ORC_MAXM];
+                        mirror_state(P, d, uj, um);
+                        orc_phys_flux(P, d, um, fm);
+                        for (int v = 0; v < M; ++v) {
+                            T->UGt[tr_index(P, e, face, k, v)] += P->b[j] * um[v];
+                            T->FGt[tr_index(P, e, face, k, v)] += P->b[j] * fm[v];
+                        }
+                    }
+                    if (T->Ust)
+                        for (int v = 0; v < M; ++v) T->Ust[st_index(P, e, face, k, j, v)] = uj[v];
                 }
             }
     free(us);
@@ -736,6 +811,11 @@ static void interface_flux(const orc_problem *P, const traces_t *T, const double
     const double *Fo = T->Ft + tr_index(P, e, face, k, 0);
     const double *Un = T->Ut + tr_index(P, en, nface, k, 0);
     const double *Fn = T->Ft + tr_index(P, en, nface, k, 0);
+    if (at_wall(P, e, d, side)) {
+        /* beyond a wall: the mirror image's traces (en = e, unn = R uno) */
+        Un = T->UGt + tr_index(P, e, face, k, 0);
+        Fn = T->FGt + tr_index(P, e, face, k, 0);
+    }
     /* left (-) and right (+) states of this interface */
     const double *UL = side ? Uo : Un, *UR = side ? Un : Uo;
     const double *FL = side ? Fo : Fn, *FR = side ? Fn : Fo;
@@ -758,16 +838,14 @@ int orc_crk_step(const orc_problem *P, const double *un, double dt, const double
 {
     if (P->N < 1 || P->N > ORC_MAXN || P->stages < 1 || P->stages > ORC_MAXS) return -1;
     if (P->limiter != ORC_LIM_NONE && P->eq != ORC_EULER) return -2;
+    if (has_walls(P) && P->eq != ORC_EULER) return -3;
     refel_t r;
     make_refel(P, &r);
-    int M = r.M, np = r.np, N = P->N, nf = nface_nodes(P), nfaces = 2 * P->dim;
+    int M = r.M, np = r.np, N = P->N, nf = nface_nodes(P);
     long E = nelem_of(P);
     double *V = malloc(sizeof(double) * E * np * M);
     traces_t T;
-    long ntr = E * nfaces * nf * M;
-    T.Ut = malloc(sizeof(double) * ntr);
-    T.Ft = malloc(sizeof(double) * ntr);
-    T.Fnct = malloc(sizeof(double) * ntr);
+    traces_alloc(P, &T);
     double *alpha = calloc(E, sizeof(double));
 
 #pragma omp parallel for num_threads(nthreads_of(P)) schedule(static)
@@ -796,7 +874,8 @@ int orc_crk_step(const orc_problem *P, const double *un, double dt, const double
         for (int d = 0; d < P->dim; ++d) {
             double idx = 1.0 / dx_of(P, d);
             for (int side = 0; side < 2; ++side) {
-                long en = neighbour(P, e, d, side);
+                long en = neighbour_or_self(P, e, d, side);
+                int wall = at_wall(P, e, d, side);
                 int face = 2 * d + side, nface = 2 * d + (1 - side);
                 double une[ORC_MAXNP * ORC_MAXM];
                 gather_elem(P, un, en, une);
@@ -807,19 +886,33 @@ int orc_crk_step(const orc_problem *P, const double *un, double dt, const double
                     const double *Fnco = T.Fnct + tr_index(P, e, face, k, 0);
                     const double *Un = T.Ut + tr_index(P, en, nface, k, 0);
                     const double *uno = ue + p * M, *unn = une + pn * M;
+                    double umir[ORC_MAXM];
+                    if (wall) {
+                        mirror_state(P, d, uno, umir);
+                        unn = umir;
+                    }
                     const double *UL = side ? Uo : Un, *UR = side ? Un : Uo;
                     double Fnum[ORC_MAXM];
                     interface_flux(P, &T, P->limiter != ORC_LIM_NONE ? alpha : NULL, e, en, d, side, k, uno, unn,
                                    Fnum);
                     for (int v = 0; v < M; ++v) Fstar[face][k][v] = Fnum[v];
-                    /* non-conservative interface flux of the own side:
-                     * 1/2 B(u^n_own) (g(U^-) + g(U^+)) */
                     double ncn[ORC_MAXM];
-                    if (P->eq == ORC_MHD) {
+                    for (int v = 0; v < M; ++v) ncn[v] = 0.0;
+                    if (P->eq == ORC_MHD && !P->nc_stagewise) {
+                        /* non-conservative interface flux of the own side, reduced
+                         * form: 1/2 B(u^n_own) (g(U^-) + g(U^+)) */
                         double gB = UL[5 + d] + UR[5 + d], gpsi = UL[8] + UR[8];
                         mhd_B_times(P, d, uno, 0.5 * gB, 0.5 * gpsi, ncn);
-                    } else {
-                        for (int v = 0; v < M; ++v) ncn[v] = 0.0;
+                    } else if (P->eq == ORC_MHD) {
+                        /* stage-wise form (eq:bad.numflux.non.cons):
+                         * sum_j b_j 1/2 B(u^(j)_own) (g(u^(j),-) + g(u^(j),+)) */
+                        for (int j = 0; j < P->stages; ++j) {
+                            const double *uo_j = T.Ust + st_index(P, e, face, k, j, 0);
+                            const double *un_j = T.Ust + st_index(P, en, nface, k, j, 0);
+                            double o[ORC_MAXM];
+                            mhd_B_times(P, d, uo_j, 0.5 * (uo_j[5 + d] + un_j[5 + d]), 0.5 * (uo_j[8] + un_j[8]), o);
+                            for (int v = 0; v < M; ++v) ncn[v] += P->b[j] * o[v];
+                        }
                     }
                     /* eq:crkfr.non.cons.final with dg_R = delta_pN/w_N, dg_L = -delta_p0/w_0 */
                     for (int v = 0; v < M; ++v) {
@@ -867,7 +960,7 @@ int orc_crk_step(const orc_problem *P, const double *un, double dt, const double
             for (int v = 0; v < M; ++v) ub[p * M + v] = (1.0 - alpha[e]) * uH[p * M + v] + alpha[e] * uLo[p * M + v];
         scatter_elem(P, unew, e, ub);
     }
-    free(V); free(T.Ut); free(T.Ft); free(T.Fnct); free(alpha);
+    free(V); traces_free(&T); free(alpha);
     return 0;
 }
 
@@ -879,8 +972,9 @@ int orc_local_phase(const orc_problem *P, const double *un, double dt, double *V
     refel_t r;
     make_refel(P, &r);
     int M = r.M, np = r.np;
-    long E = nelem_of(P);
-    traces_t T = {Ut, Ft, Fnct};
+    long E = nelem_of(P), ntr = E * 2 * P->dim * nface_nodes(P) * M;
+    traces_t T;
+    traces_alloc(P, &T);
     double *Ve = malloc(sizeof(double) * E * np * M);
 #pragma omp parallel for num_threads(nthreads_of(P)) schedule(static)
     for (long e = 0; e < E; ++e) {
@@ -889,7 +983,11 @@ int orc_local_phase(const orc_problem *P, const double *un, double dt, double *V
         local_stages(P, &r, ue, dt, Ve + e * np * M, &T, e);
     }
     for (long e = 0; e < E; ++e) scatter_elem(P, V, e, Ve + e * np * M);
+    memcpy(Ut, T.Ut, sizeof(double) * ntr);
+    memcpy(Ft, T.Ft, sizeof(double) * ntr);
+    memcpy(Fnct, T.Fnct, sizeof(double) * ntr);
     free(Ve);
+    traces_free(&T);
     return 0;
 }
 
@@ -898,35 +996,41 @@ int orc_local_phase(const orc_problem *P, const double *un, double dt, double *V
  * for no blending. */
 int orc_face_fluxes(const orc_problem *P, const double *un, double dt, const double *alpha, double *Fstar)
 {
+    if (has_walls(P) && P->eq != ORC_EULER) return -3;
     refel_t r;
     make_refel(P, &r);
-    int M = r.M, np = r.np, nf = nface_nodes(P);
-    long E = nelem_of(P), ntr = E * 2 * P->dim * nf * M;
+    int M = r.M, nf = nface_nodes(P);
+    long E = nelem_of(P);
     traces_t T;
-    T.Ut = malloc(sizeof(double) * ntr);
-    T.Ft = malloc(sizeof(double) * ntr);
-    T.Fnct = malloc(sizeof(double) * ntr);
-    double *V = malloc(sizeof(double) * E * np * M);
-    orc_local_phase(P, un, dt, V, T.Ut, T.Ft, T.Fnct);
+    traces_alloc(P, &T);
+#pragma omp parallel for num_threads(nthreads_of(P)) schedule(static)
+    for (long e = 0; e < E; ++e) {
+        double ue[ORC_MAXNP * ORC_MAXM], V[ORC_MAXNP * ORC_MAXM];
+        gather_elem(P, un, e, ue);
+        local_stages(P, &r, ue, dt, V, &T, e);
+    }
 #pragma omp parallel for num_threads(nthreads_of(P)) schedule(static)
     for (long e = 0; e < E; ++e) {
         double ue[ORC_MAXNP * ORC_MAXM], une[ORC_MAXNP * ORC_MAXM];
         gather_elem(P, un, e, ue);
         for (int d = 0; d < P->dim; ++d)
             for (int side = 0; side < 2; ++side) {
-                long en = neighbour(P, e, d, side);
+                long en = neighbour_or_self(P, e, d, side);
                 gather_elem(P, un, en, une);
                 for (int k = 0; k < nf; ++k) {
                     int p = face_node(P, d, side, k), pn = face_node(P, d, 1 - side, k);
-                    interface_flux(P, &T, alpha, e, en, d, side, k, ue + p * M, une + pn * M,
+                    double umir[ORC_MAXM];
+                    const double *unn = une + pn * M;
+                    if (at_wall(P, e, d, side)) {
+                        mirror_state(P, d, ue + p * M, umir);
+                        unn = umir;
+                    }
+                    interface_flux(P, &T, alpha, e, en, d, side, k, ue + p * M, unn,
                                    Fstar + tr_index(P, e, 2 * d + side, k, 0));
                 }
             }
     }
-    free(V);
-    free(T.Ut);
-    free(T.Ft);
-    free(T.Fnct);
+    traces_free(&T);
     return 0;
 }
 
@@ -940,6 +1044,7 @@ int orc_face_fluxes(const orc_problem *P, const double *un, double dt, const dou
 /* ------------------------------------------------------------------ */
 int orc_fr_rhs(const orc_problem *P, const double *u, int surface, double *rhs)
 {
+    if (has_walls(P) && P->eq != ORC_EULER) return -3;
     refel_t r;
     make_refel(P, &r);
     int M = r.M, np = r.np, N = P->N, nf = nface_nodes(P);
@@ -955,12 +1060,18 @@ int orc_fr_rhs(const orc_problem *P, const double *u, int surface, double *rhs)
         for (int d = 0; d < P->dim; ++d) {
             double idx = 1.0 / dx_of(P, d);
             for (int side = 0; side < 2; ++side) {
-                long en = neighbour(P, e, d, side);
+                long en = neighbour_or_self(P, e, d, side);
                 double une[ORC_MAXNP * ORC_MAXM];
                 gather_elem(P, u, en, une);
                 for (int k = 0; k < nf; ++k) {
                     int p = face_node(P, d, side, k), pn = face_node(P, d, 1 - side, k);
                     const double *uo = ue + p * M, *unb = une + pn * M;
+                    double umir[ORC_MAXM];
+                    if (at_wall(P, e, d, side)) {
+                        /* beyond a wall: the mirror image of this node */
+                        mirror_state(P, d, uo, umir);
+                        unb = umir;
+                    }
                     const double *uL = side ? uo : unb, *uR = side ? unb : uo;
                     double fnum[ORC_MAXM], fo[ORC_MAXM], nco[ORC_MAXM], ncn[ORC_MAXM];
                     if (surface == ORC_SURF_EC) {
@@ -1082,7 +1193,7 @@ int orc_labels(const orc_problem *P, const double *un, const double *uH, double 
         int nl = 0;
         list[nl++] = e;
         for (int d = 0; d < P->dim; ++d)
-            for (int side = 0; side < 2; ++side) list[nl++] = neighbour(P, e, d, side);
+            for (int side = 0; side < 2; ++side) list[nl++] = neighbour_or_self(P, e, d, side);
         for (int k = 0; k < nl; ++k) {
             double ue[ORC_MAXNP * ORC_MAXM];
             gather_elem(P, un, list[k], ue);
