@@ -435,6 +435,39 @@ def variant_mhd(crk, inputs, orc, precision, steps, warmup, threads):
             "error_after_steps": 1, "conservation": cons}
 
 
+def variant_mhd_stagewise(crk, inputs, steps, warmup, compare_steps=100):
+    """Orszag-Tang 192^2 FP64 with the stage-wise non-conservative interface
+    flux of eq:bad.numflux.non.cons against the reduced form the paper uses:
+    throughput, the extra face-node data per step, and how far the two
+    trajectories are apart after compare_steps steps from the same start."""
+    import numpy as np
+    n = 192
+    mk = lambda nc: crk.Solver(dim=2, nx=n, ny=n, degree=4, equation=crk.CRK_GLM_MHD, gamma=5.0 / 3.0,
+                               precision=crk.FP64, volume_flux=crk.VOL_DERIGS, cfl=0.4, nc_interface=nc)
+    xi, _, _ = crk.reference_element(4)
+    u0 = inputs.orszag_tang(n, n, xi)
+    s = mk(crk.NC_STAGEWISE)
+    pipe = Pipelined(s, u0)
+    el, kt = timed(pipe, steps, warmup, events=True)
+    check_admissible(s, pipe.state, "mhd stage-wise")
+    M, E, NP = s.shape
+    ndof = E * NP
+    S = 6
+    face_nodes_per_dof = 2 * 2 * (4 + 1) / NP
+    a = gpu_steps(s, u0, compare_steps)
+    b = gpu_steps(mk(crk.NC_REDUCED), u0, compare_steps)
+    return {"value": ndof * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3, "steps": steps,
+            "kernels_ms": kt, "interface_exchanges_per_step": 1,
+            # per face node: every stage's state written once and read once
+            # (the own side reads all of it, the neighbour B_d and psi of it),
+            # against the reduced form's time-averaged B_d and psi
+            "extra_face_bytes_per_dof": face_nodes_per_dof * 8.0 * (2 * S * M - 2 * 2),
+            "face_values_exchanged_per_face_node": {"stagewise": 2 * S, "reduced": 2},
+            "rel_l2_difference_from_reduced_form": rel_l2(a, b),
+            "rel_linf_difference_from_reduced_form": rel_linf(a, b),
+            "after_steps": compare_steps}
+
+
 def variant_wave1d(crk, inputs, orc):
     import numpy as np
     import torch
@@ -675,6 +708,18 @@ def main():
             v["mhd_ot192_fp32"] = variant_mhd(crk, inputs, orc, crk.FP32, 10, 2, threads)
         if want("density_wave_1d_fp64"):
             v["density_wave_1d_fp64"] = variant_wave1d(crk, inputs, orc)
+        if want("mhd_ot192_stagewise_fp64"):
+            v["mhd_ot192_stagewise_fp64"] = variant_mhd_stagewise(crk, inputs, 10, 2)
+        if want("rmi_crash_study"):
+            from paper_2604_02125_amd import robustness
+            t0 = time.perf_counter()
+            v["rmi_crash_study"] = {
+                "workload": "2D Euler Richtmyer-Meshkov 32x96 on [0,40/3]x[0,40], N=3, reflective walls, blending "
+                            "alpha_max=0.001, CFL 0.4, to t=30",
+                "runs": robustness.rmi_crash_study(), "wall_s": None,
+                "paper_context": "paper (Section 4.3, unstated hardware): stable to t=30 with the EC or KEP flux, "
+                                 "crash at about t=8.7 without"}
+            v["rmi_crash_study"]["wall_s"] = time.perf_counter() - t0
         if want("khi256_crkfr_vs_rkfr"):
             v["khi256_crkfr_vs_rkfr"] = variant_rkfr(crk, inputs, orc, 20, 2, threads, err=args.err_steps > 0)
         if want("khi64_crash_study"):

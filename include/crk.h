@@ -68,7 +68,15 @@ typedef enum {
     CRK_SURF_EC = 1        /* the volume flux f_S on the two traces            */
 } crk_surface_flux;
 
-/* Uniform Cartesian periodic mesh of nx (x ny) elements on [x0,x1] (x [y0,y1]). */
+/* Boundary of a direction of the mesh.  A reflective (slip) wall has the
+ * mirror image of the element beyond it (the state with the normal momentum
+ * negated): the Rusanov flux of the element's traces and their mirror image
+ * leaves no mass, tangential momentum or energy through the wall.  The paper
+ * states no boundary conditions for its Richtmyer-Meshkov test (Section
+ * 4.3); walls are this library's reading.  Euler only. */
+typedef enum { CRK_BC_PERIODIC = 0, CRK_BC_WALL = 1 } crk_boundary;
+
+/* Uniform Cartesian mesh of nx (x ny) elements on [x0,x1] (x [y0,y1]). */
 typedef struct {
     int dim;            /* 1 or 2                                   */
     int nx, ny;         /* elements per direction (ny ignored in 1D) */
@@ -77,7 +85,16 @@ typedef struct {
     int equation;       /* crk_equation (MHD: dim = 2)              */
     double gamma;
     int precision;      /* crk_precision                            */
+    int boundary[2];    /* crk_boundary of x and y (0: periodic)    */
 } crk_mesh_desc;
+
+/* Non-conservative interface flux of the MHD step (end of Section 2).
+ * REDUCED: 1/2 B(u^{n,+-}) (g(U^-) + g(U^+)) from the time averages U that
+ * the conservative flux exchanges anyway (the paper's choice, one exchange
+ * of the usual size).  STAGEWISE: eq:bad.numflux.non.cons,
+ * sum_j b_j 1/2 B(u^{(j),+-}) (g(u^{(j),-}) + g(u^{(j),+})), which needs
+ * every stage's traces of both sides (an s-fold larger exchange). */
+typedef enum { CRK_NC_REDUCED = 0, CRK_NC_STAGEWISE = 1 } crk_nc_interface;
 
 /* Scheme: explicit RK tableau (eq:butcher), volume flux, CFL number,
  * blending limiter.  A (stages x stages, row-major, strictly lower) and b
@@ -91,6 +108,7 @@ typedef struct {
     double cfl;                /* dt = cfl / ((N+1) max sum_d lambda_d/dx_d) */
     int limiter;               /* crk_limiter                                */
     double alpha_max, alpha_min;
+    int nc_interface;          /* crk_nc_interface (MHD; 0: reduced form)    */
 } crk_scheme_desc;
 
 typedef struct crk_solver crk_solver;

@@ -20,6 +20,8 @@ CRK_EULER, CRK_GLM_MHD = 0, 1
 VOL_CENTRAL, VOL_KG, VOL_RANOCHA, VOL_DERIGS = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 LIM_NONE, LIM_BLEND = 0, 1
+BC_PERIODIC, BC_WALL = 0, 1
+NC_REDUCED, NC_STAGEWISE = 0, 1
 SURF_RUSANOV, SURF_EC = 0, 1
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NONPHYSICAL, ERR_NOT_FINITE, ERR_STATE = 0, -1, -2, -3, -4, -5, -6
 STEP_COMPUTE_DT = 1
@@ -29,13 +31,14 @@ PHASE_LOCAL, PHASE_INTERFACE, PHASE_LOCAL_PLAIN, PHASE_LOCAL_BLEND = 1, 2, 4, 8
 class MeshDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int),
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
-                ("degree", C.c_int), ("equation", C.c_int), ("gamma", C.c_double), ("precision", C.c_int)]
+                ("degree", C.c_int), ("equation", C.c_int), ("gamma", C.c_double), ("precision", C.c_int),
+                ("boundary", C.c_int * 2)]
 
 
 class SchemeDesc(C.Structure):
     _fields_ = [("stages", C.c_int), ("A", C.POINTER(C.c_double)), ("b", C.POINTER(C.c_double)),
                 ("volume_flux", C.c_int), ("cfl", C.c_double), ("limiter", C.c_int),
-                ("alpha_max", C.c_double), ("alpha_min", C.c_double)]
+                ("alpha_max", C.c_double), ("alpha_min", C.c_double), ("nc_interface", C.c_int)]
 
 
 class CrkError(RuntimeError):
@@ -125,10 +128,12 @@ class Solver:
 
     def __init__(self, dim=2, nx=4, ny=4, x0=0.0, x1=1.0, y0=0.0, y1=1.0, degree=3, equation=CRK_EULER,
                  gamma=1.4, precision=FP64, A=None, b=None, volume_flux=VOL_RANOCHA, cfl=0.4,
-                 limiter=LIM_NONE, alpha_max=0.008, alpha_min=1e-3, device="cuda"):
+                 limiter=LIM_NONE, alpha_max=0.008, alpha_min=1e-3, boundary=(BC_PERIODIC, BC_PERIODIC),
+                 nc_interface=NC_REDUCED, device="cuda"):
         import torch
         self.device = torch.device(device)
         m = MeshDesc(dim, nx, ny, x0, x1, y0, y1, degree, equation, gamma, precision)
+        m.boundary[0], m.boundary[1] = int(boundary[0]), int(boundary[1])
         sc = SchemeDesc()
         if A is not None:
             s = len(b)
@@ -137,6 +142,7 @@ class Solver:
             sc.stages, sc.A, sc.b = s, C.cast(self._A, _dp), C.cast(self._b, _dp)
         sc.volume_flux, sc.cfl, sc.limiter = volume_flux, cfl, limiter
         sc.alpha_max, sc.alpha_min = alpha_max, alpha_min
+        sc.nc_interface = int(nc_interface)
         h = _vp()
         _check(lib().crk_create(C.byref(m), C.byref(sc), C.byref(h)), "crk_create")
         self._h = h

@@ -126,6 +126,8 @@ struct crk_solver {
     size_t elem_bytes;
     size_t state_bytes, trace_bytes;
     size_t off_partials, off_slots, off_araw, off_alpha, off_features, off_tiles, off_diag, off_traces, ws_bytes;
+    size_t off_stage;  // stage-wise non-conservative interface flux: stage states at the face nodes
+    bool stagewise;
     long ntiles;     // local-phase tiles (two flag sets of ntiles ints in the workspace)
     int tparity;     // flag set of the next local phase
     bool tiles_valid; // the flag set covers the raw coefficients in the workspace
@@ -212,6 +214,15 @@ crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables
     if (sc->limiter == CRK_LIM_BLEND && m->equation != CRK_EULER)
         return fail(CRK_ERR_UNSUPPORTED, "the blending limiter is implemented for Euler only");
     if (!(sc->cfl > 0.0)) return fail(CRK_ERR_ARG, "cfl must be positive");
+    for (int d = 0; d < 2; ++d)
+        if (m->boundary[d] != CRK_BC_PERIODIC && m->boundary[d] != CRK_BC_WALL)
+            return fail(CRK_ERR_ARG, "unknown boundary kind");
+    const bool walls = m->boundary[0] == CRK_BC_WALL || (m->dim == 2 && m->boundary[1] == CRK_BC_WALL);
+    if (walls && m->equation != CRK_EULER) return fail(CRK_ERR_UNSUPPORTED, "reflective walls are implemented for Euler only");
+    if (sc->nc_interface != CRK_NC_REDUCED && sc->nc_interface != CRK_NC_STAGEWISE)
+        return fail(CRK_ERR_ARG, "unknown non-conservative interface flux");
+    if (sc->nc_interface == CRK_NC_STAGEWISE && m->equation != CRK_GLM_MHD)
+        return fail(CRK_ERR_UNSUPPORTED, "the stage-wise non-conservative interface flux is an MHD option");
     const long nnode = m->dim == 2 ? (long)(m->degree + 1) * (m->degree + 1) : m->degree + 1;
     const long nelem = m->dim == 2 ? (long)m->nx * m->ny : m->nx;
     if (nelem * nnode >= (1L << 31)) return fail(CRK_ERR_ARG, "mesh too large");
@@ -226,6 +237,8 @@ crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables
     t.nelem = (int)nelem;
     t.nnode = (int)nnode;
     t.nface = m->dim == 2 ? m->degree + 1 : 1;
+    t.wall[0] = m->boundary[0] == CRK_BC_WALL ? 1 : 0;
+    t.wall[1] = (m->dim == 2 && m->boundary[1] == CRK_BC_WALL) ? 1 : 0;
     t.invdx[0] = m->nx / (m->x1 - m->x0);
     t.inv_nx = 1.0 / m->nx;
     t.invdx[1] = m->dim == 2 ? m->ny / (m->y1 - m->y0) : 0.0;
@@ -279,6 +292,9 @@ crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables
         t.invw_dx[1][p] = t.invdx[1] / w[p];
         for (int q = 0; q <= t.N; ++q) t.D[p][q] = D[p * (t.N + 1) + q];
     }
+    if (sc->nc_interface == CRK_NC_STAGEWISE && !((t.stages == 4 && t.tableau == 1) || (t.stages == 6 && t.tableau == 2)))
+        return fail(CRK_ERR_UNSUPPORTED,
+                    "the stage-wise interface flux is compiled for classical RK4 and Butcher's six-stage method");
     modal_inverse(t.N, xi, w, t.Vinv);
     t.ind_threshold = 0.5 * std::pow(10.0, -1.8 * std::pow(t.N + 1.0, 0.25));
     t.ind_sharpness = std::log((1.0 - 1e-4) / 1e-4);
@@ -325,6 +341,9 @@ crk_status crk_create(const crk_mesh_desc *m, const crk_scheme_desc *sc, crk_sol
     s->off_tiles = off; off = align256(off + sizeof(int) * 2 * elem_blocks);
     s->off_diag = off; off = align256(off + sizeof(double) * (t.M + 5));
     s->off_traces = off; off = align256(off + s->trace_bytes);
+    s->stagewise = sc->nc_interface == CRK_NC_STAGEWISE;
+    s->off_stage = off;
+    if (s->stagewise) off = align256(off + (size_t)2 * t.dim * t.stages * t.M * nelem * t.nface * s->elem_bytes);
     s->ws_bytes = off;
     s->ws = nullptr;
     s->prepared = false;
@@ -534,8 +553,10 @@ crk_status crk_local_stages(crk_solver *s, const void *u_in, const double *dt_de
     if (!s || !u_in || !dt_dev || !u_out || !traces) return fail(CRK_ERR_ARG, "null argument");
     if (u_in == u_out) return fail(CRK_ERR_ARG, "u_in and u_out must not alias");
     if (!is_aligned(u_in) || !is_aligned(u_out) || !is_aligned(traces)) return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
+    if (s->stagewise && !s->ws) return fail(CRK_ERR_STATE, "the stage-wise interface flux keeps its stage traces in the workspace");
     StepPtrs p{};
     p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = traces;
+    p.stage_tr = s->stagewise ? s->ws + s->off_stage : nullptr;
     p.alpha = s->limiter == CRK_LIM_BLEND ? alpha : nullptr;
     hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::face_speed(s->t, s->flux, p, (hipStream_t)stream); });
     if (e == hipSuccess)
@@ -550,8 +571,10 @@ crk_status crk_interface_update(crk_solver *s, const void *u_in, const void *tra
     if (u_in == u_inout) return fail(CRK_ERR_ARG, "u_in and u_inout must not alias");
     if (!is_aligned(u_in) || !is_aligned(u_inout) || !is_aligned(traces))
         return fail(CRK_ERR_ARG, "buffers must be 256-byte aligned");
+    if (s->stagewise && !s->ws) return fail(CRK_ERR_STATE, "the stage-wise interface flux keeps its stage traces in the workspace");
     StepPtrs p{};
     p.u_in = u_in; p.u_out = u_inout; p.dt = dt_dev; p.traces = const_cast<void *>(traces);
+    p.stage_tr = s->stagewise ? s->ws + s->off_stage : nullptr;
     hipError_t e = dispatch(s, [&](auto fam) { return decltype(fam)::interface(s->t, s->flux, p, (hipStream_t)stream); });
     return e == hipSuccess ? CRK_OK : hip_fail(e, "crk_interface_update");
 }
@@ -645,6 +668,7 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
         StepPtrs p{};
         p.instances = instances;
         p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = tr;
+        p.stage_tr = s->stagewise ? s->ws + s->off_stage : nullptr;
         p.alpha_raw = lim ? araw : nullptr;
         p.alpha_s = alpha;
         if (flags && s->tiles_valid) {
@@ -657,6 +681,7 @@ crk_status crk_advance(crk_solver *s, const void *u_in, void *u_out, double *dt_
     if (phases & CRK_PHASE_INTERFACE) {
         StepPtrs p{};
         p.u_in = u_in; p.u_out = u_out; p.dt = dt_dev; p.traces = tr;
+        p.stage_tr = s->stagewise ? s->ws + s->off_stage : nullptr;
         p.alpha_raw_out = lim ? araw : nullptr;
         p.partials = (double *)(s->ws + s->off_slots);
         p.dt_out = dt_dev;

@@ -279,8 +279,10 @@ crk_status crk_batch_create(const crk_mesh_desc *meshes, int nprob, const crk_sc
     const size_t elem = b->prec == CRK_FP64 ? 8 : 4;
     for (int i = 0; i < nprob; ++i) {
         const crk_mesh_desc &m = meshes[i];
-        if (m.dim != 2 || m.equation != CRK_EULER || (m.degree != 3 && m.degree != 4) || m.precision != b->prec) {
-            set_error(CRK_ERR_UNSUPPORTED, "batch problems must be 2D Euler of degree 3 or 4 and one precision");
+        if (m.dim != 2 || m.equation != CRK_EULER || (m.degree != 3 && m.degree != 4) || m.precision != b->prec ||
+            m.boundary[0] != CRK_BC_PERIODIC || m.boundary[1] != CRK_BC_PERIODIC) {
+            set_error(CRK_ERR_UNSUPPORTED,
+                      "batch problems must be periodic 2D Euler of degree 3 or 4 and one precision");
             delete b;
             return CRK_ERR_UNSUPPORTED;
         }

@@ -57,6 +57,7 @@ __device__ __forceinline__ long xcd_chunk_tile(long b, long G)
 // Everything a kernel needs besides its pointers; passed by value.
 struct Tables {
     int dim, nx, ny, N, M, nelem, nnode, nface;  // nface = nodes per face
+    int wall[2];                      // per direction: reflective walls instead of periodic wrap
     double invdx[2];
     double inv_nx;                    // 1/nx, for the element coordinates
     double gamma;
@@ -121,6 +122,10 @@ struct StepPtrs {
     // blending code, bit 1 the one with it (0: both); either launches only
     // where the configuration uses it
     int instances;
+    // MHD with the stage-wise non-conservative interface flux: the stage
+    // states u^(j) at the face nodes, [face][j][v][e][k] (local phase
+    // writes, interface phase reads); nullptr: the reduced form
+    void *stage_tr;
 };
 
 // Pointers of one stage of the standard multi-stage RKFR step (crk_rhs.hpp).
@@ -136,9 +141,14 @@ struct RkPtrs {
 // element coordinates and the four (two in 1D) face neighbours; e < 2^31.
 // The row index comes from a double-precision product with 1/nx (off by at
 // most one next to exact multiples, then corrected): far cheaper per lane
-// than a 64-bit integer division.
+// than a 64-bit integer division.  A face on a reflective wall has the
+// element itself as neighbour (beyond the wall lies its mirror image, whose
+// blending coefficient and wave speeds are the element's own) and its bit
+// 2d + side set in `wall`: the kernels that read the neighbour's state or
+// face data take the mirror image there instead.
 struct Nbrs {
     long n[2][2];   // [d][side]
+    int wall;       // bit 2d + side: that face lies on a wall
 };
 template <int DIM>
 __device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
@@ -146,9 +156,11 @@ __device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
     Nbrs r;
     const int nx = t.nx, ei = (int)e;
     if constexpr (DIM == 1) {
-        r.n[0][0] = ei == 0 ? nx - 1 : ei - 1;
-        r.n[0][1] = ei + 1 == nx ? 0 : ei + 1;
+        const bool w0 = t.wall[0] && ei == 0, w1 = t.wall[0] && ei + 1 == nx;
+        r.n[0][0] = w0 ? ei : (ei == 0 ? nx - 1 : ei - 1);
+        r.n[0][1] = w1 ? ei : (ei + 1 == nx ? 0 : ei + 1);
         r.n[1][0] = r.n[1][1] = e;
+        r.wall = (w0 ? 1 : 0) | (w1 ? 2 : 0);
         return r;
     }
     int ey = (int)floor((double)ei * t.inv_nx);
@@ -156,10 +168,13 @@ __device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
     if (ex < 0) { --ey; ex += nx; }
     else if (ex >= nx) { ++ey; ex -= nx; }
     const int row = ey * nx;
-    r.n[0][0] = row + (ex == 0 ? nx - 1 : ex - 1);
-    r.n[0][1] = row + (ex + 1 == nx ? 0 : ex + 1);
-    r.n[1][0] = (ey == 0 ? (t.ny - 1) * nx : row - nx) + ex;
-    r.n[1][1] = (ey + 1 == t.ny ? 0 : row + nx) + ex;
+    const bool wx0 = t.wall[0] && ex == 0, wx1 = t.wall[0] && ex + 1 == nx;
+    const bool wy0 = t.wall[1] && ey == 0, wy1 = t.wall[1] && ey + 1 == t.ny;
+    r.n[0][0] = wx0 ? ei : row + (ex == 0 ? nx - 1 : ex - 1);
+    r.n[0][1] = wx1 ? ei : row + (ex + 1 == nx ? 0 : ex + 1);
+    r.n[1][0] = wy0 ? ei : (ey == 0 ? (t.ny - 1) * nx : row - nx) + ex;
+    r.n[1][1] = wy1 ? ei : (ey + 1 == t.ny ? 0 : row + nx) + ex;
+    r.wall = (wx0 ? 1 : 0) | (wx1 ? 2 : 0) | (wy0 ? 4 : 0) | (wy1 ? 8 : 0);
     return r;
 }
 __device__ __forceinline__ Nbrs neighbours_any(const Tables &t, long e)
@@ -316,7 +331,10 @@ struct LocalShape {
 // BLEND = false: no blending coefficient can be positive in the tile (no
 // limiter, or a flagged-clear tile of the pipelined step); the blending code
 // is compiled out, which frees registers for a fourth wavefront per SIMD.
-template <typename real, int EQ, int DIM, int N, int FLUX, int S, int BLK, int TAB = 0, bool BLEND = true>
+// NCS (MHD): the stage-wise non-conservative interface flux (stage states
+// written at the face nodes for the interface phase) instead of the reduced form.
+template <typename real, int EQ, int DIM, int N, int FLUX, int S, int BLK, int TAB = 0, bool BLEND = true,
+          bool NCS = false>
 __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, long e0, real *smem, int lane = -1)
 {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
@@ -352,6 +370,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 
     const Ctx<real> ctx = make_ctx<real>(t, a.dt);
     const real rdt = real(a.dt[0]);
+    constexpr bool stagewise = EQ == EQ_MHD && NCS;
 
     // per-lane coefficients 2 D_{p,q}/dx_d of rotation k = 1..N, of the diagonal,
     // and 1/(w_p dx_d), read from the tables with the lane's node index
@@ -411,7 +430,9 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
             const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
             const long en = side[d] ? nb.n[d][1] : nb.n[d][0];
             const real so = ts[((long)(face * FD::NCT + FD::SPEED) * E + es) * nfn + kk];
-            const real sn = ts[((long)(nface * FD::NCT + FD::SPEED) * E + en) * nfn + kk];
+            // beyond a wall, the mirror image has the element's own wave speed
+            const bool wl = (nb.wall >> face) & 1;
+            const real sn = wl ? so : ts[((long)(nface * FD::NCT + FD::SPEED) * E + en) * nfn + kk];
             real lam = dmax(so, sn);
             if constexpr (EQ == EQ_MHD) lam = dmax(lam, ctx.ch);
             llds[d * BLK + tid] = lam;
@@ -526,6 +547,19 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 #pragma unroll
             for (int d = 0; d < DIM; ++d) UB[d] += bi * us[5 + d];
             Upsi += bi * us[8];
+            if (stagewise && valid) {
+                // stage-wise interface flux: this stage's state at the face nodes
+                real *st = (real *)a.stage_tr;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) {
+                    if (!onface[d]) continue;
+                    const int face = 2 * d + side[d];
+                    const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
+#pragma unroll
+                    for (int v = 0; v < M; ++v)
+                        st[(((long)(face * S + i) * M + v) * E + e) * nfn + kk] = us[v];
+                }
+            }
         }
         real nd[NF];
         Phys::node(us, nd, ctx);
@@ -615,10 +649,11 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                     }
                 }
                 if constexpr (EQ == EQ_MHD) {
-                    // own non-conservative trace term, b_i B_d(u^(i)) g_d(u^(i))
+                    // own non-conservative trace term, b_i B_d(u^(i)) g_d(u^(i));
+                    // the stage-wise interface flux's own half is half of it
                     real o[M];
                     MhdP<real, FLUX>::btimes(d, nd, nd[5 + d], nd[8], o);
-                    const real go = bi * sw[d];
+                    const real go = stagewise ? real(0.5) * bi * sw[d] : bi * sw[d];
 #pragma unroll
                     for (int v = 0; v < M; ++v) W[v] += go * o[v];
                 }
@@ -733,7 +768,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     }
 
     if (!valid) return;
-    if constexpr (EQ == EQ_MHD) {
+    if (EQ == EQ_MHD && !stagewise) {
         // own half of 1/2 B(u^n)(g(U^-) + g(U^+))
         real ndo[NF];
         Phys::node_basic(un, ndo, ctx);
@@ -770,7 +805,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 // clears every tile's flag of the next step) and the BLEND = true instance,
 // launched after it, the flagged ones; a workgroup leaves at once on a tile
 // of the other kind.
-template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB = 0, bool BLEND = true>
+template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB = 0, bool BLEND = true, bool NCS = false>
 __global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 1>()) k_local(const Tables t, const StepPtrs a)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
@@ -784,7 +819,7 @@ __global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 
         }
         if (BLEND ? flagged == 0 : flagged != 0) return;
     }
-    local_tile<real, EQ, DIM, N, FLUX, S, TB, TAB, BLEND>(t, a, (long)tile * (TB / NP), smem);
+    local_tile<real, EQ, DIM, N, FLUX, S, TB, TAB, BLEND, NCS>(t, a, (long)tile * (TB / NP), smem);
 }
 
 // ---------------------------------------------------------------- K8 helper: modal indicator
@@ -973,7 +1008,7 @@ constexpr int DT_SLOTS = 256;
 // pipelined step the tile's wave-speed maximum goes to partials[slot] (with
 // SLOTS: is merged into partials[slot mod DT_SLOTS]); dsmem holds 5 * BLK
 // doubles.
-template <typename real, int EQ, int DIM, int N, int FLUX, int BLK, bool SLOTS = false>
+template <typename real, int EQ, int DIM, int N, int FLUX, int BLK, bool SLOTS = false, bool NCS = false>
 __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &a, long e0, long slot, double *dsmem)
 {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
@@ -1033,16 +1068,47 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
             const long en = side ? nb.n[d][1] : nb.n[d][0];
             const int nface = 2 * d + 1 - side;
             const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
-            const real *tn = tr + ((long)nface * FD::NCT * E + en) * nf + kk;
+            // Beyond a wall lies the mirror image R u of the element (R
+            // negates the normal momentum), whose share is -R P of the
+            // element's own P: f_d(R u) = -R f_d(u) for every state, so both
+            // the time averages and the first-order part mirror that way.
+            const bool wl = (nb.wall >> (2 * d + side)) & 1;
+            const real *tn = wl ? tr + ((long)(2 * d + side) * FD::NCT * E + e) * nf + kk
+                                : tr + ((long)nface * FD::NCT * E + en) * nf + kk;
             real jump[M];
 #pragma unroll
-            for (int v = 0; v < M; ++v) jump[v] = tn[((long)v * E) * nf];
+            for (int v = 0; v < M; ++v) {
+                const real x = tn[((long)v * E) * nf];
+                jump[v] = (wl && v != 1 + d) ? -x : x;
+            }
             if constexpr (EQ == EQ_MHD) {
-                real o[M];
-                MhdP<real, FLUX>::btimes(d, ndo, real(0.5) * tn[((long)M * E) * nf],
-                                         real(0.5) * tn[((long)(M + 1) * E) * nf], o);
+                if constexpr (!NCS) {
+                    // reduced form: the neighbour's half of 1/2 B(u^n)(g(U^-) + g(U^+))
+                    real o[M];
+                    MhdP<real, FLUX>::btimes(d, ndo, real(0.5) * tn[((long)M * E) * nf],
+                                             real(0.5) * tn[((long)(M + 1) * E) * nf], o);
 #pragma unroll
-                for (int v = 0; v < M; ++v) jump[v] += o[v];
+                    for (int v = 0; v < M; ++v) jump[v] += o[v];
+                } else {
+                    // stage-wise form (eq:bad.numflux.non.cons): the neighbour's half
+                    // sum_j b_j 1/2 B(u^(j)_own) g(u^(j)_nb), from the stage states
+                    // that both local phases left at the face nodes
+                    const real *st = (const real *)a.stage_tr;
+                    const int S = t.stages;
+                    for (int j = 0; j < S; ++j) {
+                        real uj[M], ndj[NF], o[M];
+                        const real *so = st + ((long)((2 * d + side) * S + j) * M * E + e) * nf + kk;
+                        const real *sn = st + ((long)(nface * S + j) * M * E + en) * nf + kk;
+#pragma unroll
+                        for (int v = 0; v < M; ++v) uj[v] = so[(long)v * E * nf];
+                        Phys::node_basic(uj, ndj, ctx);
+                        MhdP<real, FLUX>::btimes(d, ndj, real(0.5) * sn[(long)(5 + d) * E * nf],
+                                                 real(0.5) * sn[(long)8 * E * nf], o);
+                        const real bj = real(t.b[j]);
+#pragma unroll
+                        for (int v = 0; v < M; ++v) jump[v] += bj * o[v];
+                    }
+                }
             }
             const real coef = rdt * real(t.invw_dx[d][side ? N : 0]);
 #pragma unroll
@@ -1088,13 +1154,13 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
     else block_max_lanes<BLK>(sp, dsmem, a.partials + slot);
 }
 
-template <typename real, int EQ, int DIM, int N, int FLUX>
+template <typename real, int EQ, int DIM, int N, int FLUX, bool NCS = false>
 __global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 1>()) k_interface(const Tables t, const StepPtrs a)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     constexpr int TB = tile_block<NP>();
     __shared__ double dsmem[5 * TB];
-    interface_tile<real, EQ, DIM, N, FLUX, TB, true>(t, a, xcd_tile(blockIdx.x, gridDim.x) * (TB / NP), blockIdx.x, dsmem);
+    interface_tile<real, EQ, DIM, N, FLUX, TB, true, NCS>(t, a, xcd_tile(blockIdx.x, gridDim.x) * (TB / NP), blockIdx.x, dsmem);
 }
 
 // dt = cfl / ((N+1) m) from the global wave-speed maximum m (MHD: m = c_h and
@@ -1402,6 +1468,19 @@ hipError_t launch_local(const Tables &t, const StepPtrs &p, hipStream_t s)
     // without blending coefficients (no limiter) every tile takes the
     // instance without the blending code; with tile flags both run, the
     // blending one second; with given coefficients only the blending one
+    if constexpr (EQ == EQ_MHD) {
+        if (p.stage_tr != nullptr) {
+            // stage-wise non-conservative interface flux: the default tableaus only
+            if (!(p.instances == 0 || (p.instances & 1))) return hipSuccess;
+            if (t.stages == 4 && t.tableau == 1)
+                hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 1, false, true>), dim3(grid), dim3(TB), 0, s, t, p);
+            else if (t.stages == 6 && t.tableau == 2)
+                hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6, 2, false, true>), dim3(grid), dim3(TB), 0, s, t, p);
+            else
+                return hipErrorInvalidValue;
+            return hipGetLastError();
+        }
+    }
     const bool blend = p.alpha != nullptr || p.alpha_raw != nullptr;
     const int which = p.instances ? p.instances : 3;
     if ((which & 1) && (!blend || p.tiles_in != nullptr)) {
@@ -1431,7 +1510,10 @@ hipError_t launch_interface(const Tables &t, const StepPtrs &p, hipStream_t s)
     constexpr int TB = tile_block<NP>();
     constexpr int EPB = TB / NP;
     const int grid = (t.nelem + EPB - 1) / EPB;
-    hipLaunchKernelGGL((k_interface<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(TB), 0, s, t, p);
+    if (EQ == EQ_MHD && p.stage_tr != nullptr)
+        hipLaunchKernelGGL((k_interface<real, EQ, DIM, N, FLUX, true>), dim3(grid), dim3(TB), 0, s, t, p);
+    else
+        hipLaunchKernelGGL((k_interface<real, EQ, DIM, N, FLUX>), dim3(grid), dim3(TB), 0, s, t, p);
     if (p.dt_out != nullptr)
         hipLaunchKernelGGL(k_dt_slots, dim3(1), dim3(64), 0, s, t, p.partials, EQ == EQ_MHD ? 1 : 0, p.dt_out);
     return hipGetLastError();

@@ -138,8 +138,14 @@ __device__ __forceinline__ void rhs_lane(const Tables &t, const real *u, const C
         pn[d] = N - pd[d];
         const int nn = DIM == 2 ? pn[1] * n1 + pn[0] : pn[0];
         real un[M], ndn[NF];
+        if ((nb.wall >> (2 * d + side)) & 1) {
+            // beyond a wall: the mirror image of this node (normal momentum negated)
 #pragma unroll
-        for (int v = 0; v < M; ++v) un[v] = u[((long)v * E + en) * NP + nn];
+            for (int v = 0; v < M; ++v) un[v] = v == 1 + d ? -uo[v] : uo[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < M; ++v) un[v] = u[((long)v * E + en) * NP + nn];
+        }
         Phys::node(un, ndn, ctx);
         // left and right traces (selects, no indexing of register arrays by side)
         real aL[NF], aR[NF], uL[M], uR[M];

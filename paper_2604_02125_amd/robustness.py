@@ -65,3 +65,23 @@ def khi_crash_study(fluxes=(crk.VOL_CENTRAL, crk.VOL_KG, crk.VOL_RANOCHA), n=64,
         u0 = inputs.kelvin_helmholtz(n, n, xi, rho_base=rho_base)
         out[names[f]] = run_until(s, u0, t_end, check_every=check_every)
     return out
+
+
+def rmi_crash_study(fluxes=(crk.VOL_CENTRAL, crk.VOL_KG, crk.VOL_RANOCHA), nx=32, ny=96, t_end=30.0,
+                    alpha_max=0.001, precision=crk.FP64, check_every=100):
+    """Section 4.3: compressible Euler Richtmyer-Meshkov instability on
+    [0, 40/3] x [0, 40], nx x ny elements of degree 3, blending limiter with
+    alpha_max, reflective walls on all four sides (the paper gives no
+    boundary conditions; the initial state is mirror-symmetric about the
+    vertical walls, so there they agree with a periodic continuation), run
+    to t_end once per volume flux."""
+    names = {crk.VOL_CENTRAL: "central", crk.VOL_KG: "kennedy_gruber", crk.VOL_RANOCHA: "ranocha"}
+    out = {}
+    for f in fluxes:
+        s = crk.Solver(dim=2, nx=nx, ny=ny, x0=0.0, x1=40.0 / 3.0, y0=0.0, y1=40.0, degree=3, precision=precision,
+                       volume_flux=f, cfl=0.4, limiter=crk.LIM_BLEND, alpha_max=alpha_max, alpha_min=1e-3,
+                       boundary=(crk.BC_WALL, crk.BC_WALL))
+        xi, _, _ = crk.reference_element(3)
+        u0 = inputs.richtmyer_meshkov(nx, ny, xi)
+        out[names[f]] = run_until(s, u0, t_end, check_every=check_every)
+    return out
