@@ -402,11 +402,14 @@ def variant_batch(crk, inputs, orc, precision, reps, err_sample=4):
         den += float(np.sum(ref ** 2))
         dmax = max(dmax, float(np.max(np.abs(got - ref))))
         rmax = max(rmax, float(np.max(np.abs(ref))))
-    return {"value": b.ndof / (ms * 1e-3), "unit": "DOF-updates/s", "ms_per_step": ms, "steps": 2 * reps,
-            "problems": len(specs), "dofs": b.ndof, "tuning": {"block": b.tuning[0], "grid_per_cu": b.tuning[1]},
-            "graph": "2 pipelined steps per replay",
-            "l2_rel_error_vs_fp64_oracle": float(np.sqrt(num / den)), "linf_rel_error_vs_fp64_oracle": dmax / rmax,
-            "error_after_steps": 2, "error_sample": f"first {err_sample} problems"}
+    out = {"value": b.ndof / (ms * 1e-3), "unit": "DOF-updates/s", "ms_per_step": ms, "steps": 2 * reps,
+           "problems": len(specs), "dofs": b.ndof, "tuning": {"block": b.tuning[0], "grid_per_cu": b.tuning[1], "merged": b.tuning[2]},
+           "graph": "2 pipelined steps per replay"}
+    if err_sample:
+        out.update({"l2_rel_error_vs_fp64_oracle": float(np.sqrt(num / den)),
+                    "linf_rel_error_vs_fp64_oracle": dmax / rmax,
+                    "error_after_steps": 2, "error_sample": f"first {err_sample} problems"})
+    return out
 
 
 def variant_mhd(crk, inputs, orc, precision, steps, warmup, threads):

@@ -344,8 +344,9 @@ crk_status crk_set_mlp(crk_solver *s, const uint16_t *theta_bf16, const float *f
  * degree 4 with Butcher's RK5, one precision, Kennedy-Gruber or Ranocha
  * volume flux, no limiter) advanced together by pipelined steps.  The
  * element tiles of all problems form one work list (degree-3 tiles first);
- * each phase is one launch per degree over the tiles of that degree, with
- * one workgroup per tile or a fixed grid of persistent workgroups (tuning);
+ * each phase is one launch per degree over the tiles of that degree, or one
+ * launch over all of them (tuning.merged), with one workgroup per tile or a
+ * fixed grid of persistent workgroups (tuning);
  * each problem has its own CFL time step.  Each problem i occupies the values
  * [offsets[i], offsets[i+1]) of a state buffer, laid out as u[v][e][node]
  * of that problem. */
@@ -353,6 +354,8 @@ typedef struct crk_batch crk_batch;
 typedef struct {
     int block;          /* lanes per workgroup: 64, 128 or 256 (0: 256)           */
     int grid_per_cu;    /* persistent workgroups per compute unit; 0: one per tile */
+    int merged;         /* 1: one launch per phase over the tiles of both degrees,
+                           each tile taking its degree's path; 0: one per degree  */
 } crk_batch_tuning;
 /* meshes[nprob]; scheme->A and ->b must be NULL.  tuning may be NULL. */
 crk_status crk_batch_create(const crk_mesh_desc *meshes, int nprob, const crk_scheme_desc *scheme,

@@ -287,7 +287,7 @@ class Solver:
 
 
 class BatchTuning(C.Structure):
-    _fields_ = [("block", C.c_int), ("grid_per_cu", C.c_int)]
+    _fields_ = [("block", C.c_int), ("grid_per_cu", C.c_int), ("merged", C.c_int)]
 
 
 TUNING_PATH = os.path.join(HERE, "tuning.json")
@@ -302,7 +302,7 @@ def load_tuning(precision: int, volume_flux: int):
         tab = json.load(fh)
     key = f"{'fp64' if precision == FP64 else 'fp32'}/{ {VOL_KG: 'kg', VOL_RANOCHA: 'ranocha'}.get(volume_flux, '?') }"
     rec = tab.get("batch", {}).get(key)
-    return None if rec is None else (int(rec["block"]), int(rec["grid_per_cu"]))
+    return None if rec is None else (int(rec["block"]), int(rec["grid_per_cu"]), int(rec.get("merged", 0)))
 
 
 def _bind_batch_functions(L):
@@ -348,8 +348,8 @@ class Batch:
         sc.volume_flux, sc.cfl, sc.limiter = volume_flux, cfl, LIM_NONE
         if tuning is None:
             tuning = load_tuning(precision, volume_flux)
-        tn = BatchTuning(*(tuning if tuning is not None else (256, 4)))
-        self.tuning = (tn.block, tn.grid_per_cu)
+        tn = BatchTuning(*(tuning if tuning is not None else (256, 4, 0)))
+        self.tuning = (tn.block, tn.grid_per_cu, tn.merged)
         h = _vp()
         _check(L.crk_batch_create(meshes, self.nprob, C.byref(sc), C.byref(tn), C.byref(h)), "crk_batch_create")
         self._h = h

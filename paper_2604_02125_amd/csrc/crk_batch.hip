@@ -43,17 +43,29 @@ struct BatchTile {
 // persistent loop the lane index passes through an empty asm statement so
 // that the compiler recomputes the lane's per-node constants in every
 // iteration instead of keeping them live across the whole loop.
+// NDEG = 0: one launch over the whole work list, each tile taking the
+// degree-3 or degree-4 path by its problem's degree (the kernel then has the
+// degree-4 path's register budget for every tile).
+template <typename real, int FLUX, int NDEG>
+struct BatchLocalLds {
+    static constexpr int s3 = LocalShape<real, EQ_EULER, 2, 3, FLUX>::slots;
+    static constexpr int s4 = LocalShape<real, EQ_EULER, 2, 4, FLUX>::slots;
+    static constexpr int slots = NDEG == 3 ? s3 : (NDEG == 4 ? s4 : (s3 > s4 ? s3 : s4));
+};
+
 template <typename real, int FLUX, int BLK, int NDEG, bool PERSIST>
 __global__ void __launch_bounds__(BLK) k_batch_local(const BatchProblem *probs, const BatchTile *tiles, int t0, int t1,
                                                      int dir)
 {
-    __shared__ real smem[LocalShape<real, EQ_EULER, 2, NDEG, FLUX>::slots * BLK];
+    __shared__ real smem[BatchLocalLds<real, FLUX, NDEG>::slots * BLK];
     auto tile = [&](int it, int lane) {
         const BatchTile tl = tiles[it];
         const BatchProblem &bp = probs[tl.prob];
         // batches have no limiter: the instance without the blending code
-        if constexpr (NDEG == 3) local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK, 1, false>(bp.t, bp.p[dir], tl.e0, smem, lane);
-        else local_tile<real, EQ_EULER, 2, 4, FLUX, 6, BLK, 2, false>(bp.t, bp.p[dir], tl.e0, smem, lane);
+        if (NDEG == 3 || (NDEG == 0 && bp.t.N == 3))
+            local_tile<real, EQ_EULER, 2, 3, FLUX, 4, BLK, 1, false>(bp.t, bp.p[dir], tl.e0, smem, lane);
+        else
+            local_tile<real, EQ_EULER, 2, 4, FLUX, 6, BLK, 2, false>(bp.t, bp.p[dir], tl.e0, smem, lane);
     };
     if constexpr (PERSIST) {
         for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
@@ -77,7 +89,10 @@ __global__ void __launch_bounds__(BLK) k_batch_interface(const BatchProblem *pro
     auto tile = [&](int it) {
         const BatchTile tl = tiles[it];
         const BatchProblem &bp = probs[tl.prob];
-        interface_tile<real, EQ_EULER, 2, NDEG, FLUX, BLK>(bp.t, bp.p[dir], tl.e0, it, dsmem);
+        if (NDEG == 3 || (NDEG == 0 && bp.t.N == 3))
+            interface_tile<real, EQ_EULER, 2, 3, FLUX, BLK>(bp.t, bp.p[dir], tl.e0, it, dsmem);
+        else
+            interface_tile<real, EQ_EULER, 2, 4, FLUX, BLK>(bp.t, bp.p[dir], tl.e0, it, dsmem);
     };
     if constexpr (PERSIST) {
         for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
@@ -162,7 +177,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 } // namespace
 
 struct crk_batch {
-    int nprob, prec, flux, block, grid;
+    int nprob, prec, flux, block, grid, merged;
     std::vector<crk_mesh_desc> mesh;
     std::vector<BatchProblem> probs;     // host copy of the descriptors
     std::vector<BatchTile> tiles;        // degree-3 problems' tiles first, then degree 4
@@ -191,10 +206,14 @@ hipError_t launch_phase(const crk_batch *b, int kind, int dir, hipStream_t s)
     const int n3 = b->ntiles3, n4 = nt - n3;
     const bool pers = b->grid > 0;
     auto grid_of = [&](int n) { return dim3(pers && b->grid < n ? b->grid : n); };
-    // one launch per degree and phase: the degree-3 tiles [0, n3), then the degree-4 ones [n3, nt)
+    // one launch per degree and phase: the degree-3 tiles [0, n3), then the
+    // degree-4 ones [n3, nt); merged: one launch over [0, nt)
 #define CRK_BATCH_PHASE(K)                                                                                  \
     do {                                                                                                    \
-        if (pers) {                                                                                         \
+        if (b->merged) {                                                                                    \
+            if (pers) hipLaunchKernelGGL((K<real, FLUX, BLK, 0, true>), grid_of(nt), dim3(BLK), 0, s, pr, tl, 0, nt, dir); \
+            else hipLaunchKernelGGL((K<real, FLUX, BLK, 0, false>), dim3(nt), dim3(BLK), 0, s, pr, tl, 0, nt, dir);        \
+        } else if (pers) {                                                                                  \
             if (n3 > 0) hipLaunchKernelGGL((K<real, FLUX, BLK, 3, true>), grid_of(n3), dim3(BLK), 0, s, pr, tl, 0, n3, dir);  \
             if (n4 > 0) hipLaunchKernelGGL((K<real, FLUX, BLK, 4, true>), grid_of(n4), dim3(BLK), 0, s, pr, tl, n3, nt, dir); \
         } else {                                                                                            \
@@ -320,6 +339,7 @@ crk_status crk_batch_create(const crk_mesh_desc *meshes, int nprob, const crk_sc
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     }
     const int gpc = tuning ? tuning->grid_per_cu : 4;
+    b->merged = tuning ? (tuning->merged ? 1 : 0) : 0;
     b->grid = gpc > 0 ? gpc * cus : 0;   // 0: one workgroup per tile
     size_t w = 0;
     b->off_probs = w; w = align256(w + sizeof(BatchProblem) * nprob);

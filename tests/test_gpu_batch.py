@@ -36,7 +36,7 @@ def _fill(orc, batch, seed):
     return states
 
 
-@pytest.mark.parametrize("tuning", [(256, 4), (128, 0), (64, 2)])
+@pytest.mark.parametrize("tuning", [(256, 4), (128, 0), (64, 2), (128, 0, 1), (64, 32, 1)])
 def test_batch_matches_oracle_per_problem(orc, tuning):
     b = crk.Batch(SPECS, tuning=tuning)
     u0 = _fill(orc, b, seed=1)
