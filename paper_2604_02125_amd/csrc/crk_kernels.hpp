@@ -323,7 +323,13 @@ struct LocalShape {
     // the exchange cost as much as the pair.)
     static constexpr bool BAL = DIM == 2 && SYM && KSELF > 0 && EQ == EQ_EULER && FLUX == VOL_RANOCHA;
     static constexpr int XB = BAL ? Phys::M : 0;
-    static constexpr int slots = Phys::NF + NX + ASL + DIM + CS + XB;
+    // degree 4 in 2D (256-lane workgroups, workgroup barriers): the node
+    // fields alternate between two sets of slots from stage to stage, so that
+    // a stage may overwrite them without waiting for the previous stage's
+    // readers (one barrier fewer per stage; the LDS this adds does not lower
+    // the occupancy of these register-bound kernels)
+    static constexpr bool DBF = DIM == 2 && N == 4;
+    static constexpr int slots = (DBF ? 2 : 1) * Phys::NF + NX + ASL + DIM + CS + XB;
 };
 
 // One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
@@ -347,8 +353,9 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     constexpr bool SYM = Shape::SYM;
     constexpr int NPRIM = Shape::NPRIM;
     constexpr int KSELF = Shape::KSELF;
-    real *lds = smem;                // [NF][BLK]
-    real *xch = smem + NF * BLK;     // [NX][BLK]
+    constexpr bool DBF = Shape::DBF;
+    real *lds0 = smem;                               // [NF][BLK] (two sets with DBF)
+    real *xch = smem + (DBF ? 2 : 1) * NF * BLK;     // [NX][BLK]
     real *alds = xch + Shape::NX * BLK;   // [EPB][2 DIM + 1]
     real *llds = alds + Shape::ASL * BLK; // [DIM][BLK]
     real *clds = llds + DIM * BLK;        // [CS][BLK]
@@ -563,7 +570,8 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         }
         real nd[NF];
         Phys::node(us, nd, ctx);
-        if (i > 0) element_sync<NP>();    // the previous stage has finished reading LDS
+        real *lds = lds0 + ((DBF && (i & 1)) ? NF * BLK : 0);
+        if (i > 0 && !DBF) element_sync<NP>();    // the previous stage has finished reading LDS
 #pragma unroll
         for (int f = 0; f < NF; ++f) lds[f * BLK + tid] = nd[f];
         element_sync<NP>();

@@ -124,6 +124,52 @@ def confusion(net, X, Y, alpha_max=0.008, alpha_min=1e-3):
     return {"tp": tp, "tn": tn, "fp": fp, "fn": fn, "accuracy": (tp + tn) / max(tp + tn + fp + fn, 1.0)}
 
 
+def held_out(net, seeds=(101, 102), n=128, t_snaps=(1.5, 2.5), tol=1e-5):
+    """The troubled-cell labels of snapshots from runs the network was not
+    trained on (seeds outside 1..16) against the raw blending coefficients of
+    the network and of the modal indicator on the same states: per
+    indicator, how many labelled elements it flags (tp), misses (fn), and
+    how many unlabelled ones it flags (fp)."""
+    import numpy as np
+    import torch
+
+    from paper_2604_02125_amd import crk, inputs
+    s = khi_solver(n)
+    sn = khi_solver(n)
+    net.bind(sn)
+    xi, _, _ = crk.reference_element(3)
+    zero_alpha = torch.zeros(s.nelem, dtype=torch.float64, device="cuda")
+    stats = {k: {"tp": 0, "fn": 0, "fp": 0, "tn": 0} for k in ("network", "modal")}
+    for seed in seeds:
+        u = [torch.tensor(inputs.kelvin_helmholtz(n, n, xi, v2_modes=inputs.khi_modes(seed)), device="cuda"),
+             s.new_state()]
+        uh = s.new_state()
+        dt, dt_h = s.new_dt(), s.new_dt()
+        s.prepare(u[0], dt)
+        t, k = 0.0, 0
+        for ts in t_snaps:
+            while t < ts:
+                t += dt[0].item()
+                s.advance(u[k % 2], u[(k + 1) % 2], dt)
+                k += 1
+            cur = u[k % 2]
+            s.step(cur, uh, dt_h, alpha=zero_alpha, compute_dt=True)
+            lab = crk.labels(s, cur, uh, tol=tol).cpu().numpy() > 0.5
+            s.prepare(cur, dt)
+            for name, solver in (("network", sn), ("modal", s)):
+                pred = solver.indicator(cur)[0].cpu().numpy() > 0.0
+                st = stats[name]
+                st["tp"] += int(np.sum(pred & lab))
+                st["fn"] += int(np.sum(~pred & lab))
+                st["fp"] += int(np.sum(pred & ~lab))
+                st["tn"] += int(np.sum(~pred & ~lab))
+            s.prepare(cur, dt)
+    for st in stats.values():
+        st["miss_rate"] = st["fn"] / max(st["tp"] + st["fn"], 1)
+        st["flagged_fraction"] = (st["tp"] + st["fp"]) / max(sum(st[k] for k in ("tp", "fn", "fp", "tn")), 1)
+    return stats
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["train"])

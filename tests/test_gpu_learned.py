@@ -181,6 +181,60 @@ def test_gain_over_modal_indicator(orc):
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_gain_on_held_out_labels():
+    """The modal indicator as judge, on runs the network never saw (seeds 101
+    and 102, snapshots at t = 1.5 and 2.5, KHI 128^2): against the
+    a-posteriori troubled-element labels the network must flag at least as
+    many labelled elements as the modal indicator (a bounded miss rate: not
+    above the modal one) while flagging fewer elements in all."""
+    from paper_2604_02125_amd import learned
+    st = learned.held_out(crk.MLP.load(WEIGHTS))
+    net, mod = st["network"], st["modal"]
+    print(f"held-out labels: network tp {net['tp']} fn {net['fn']} fp {net['fp']} (flagged "
+          f"{net['flagged_fraction']:.4f}); modal tp {mod['tp']} fn {mod['fn']} fp {mod['fp']} "
+          f"(flagged {mod['flagged_fraction']:.4f})")
+    assert net["tp"] + net["fn"] > 100                      # enough troubled elements to judge
+    assert net["miss_rate"] <= mod["miss_rate"]
+    assert net["flagged_fraction"] < mod["flagged_fraction"]
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+def test_gain_closer_to_unlimited_solution():
+    """KHI 128^2 to t = 2 with one fixed time step for all runs: the unlimited
+    high-order run (no blending) is the reference, since every blended
+    element adds first-order dissipation to it.  With the network the run
+    stays closer to it than with the modal indicator, and blends less."""
+    from paper_2604_02125_amd import learned
+    n = 128
+    xi, _, _ = crk.reference_element(3)
+    u0 = torch.tensor(inputs.kelvin_helmholtz(n, n, xi), device="cuda")
+    h = 0.8 * learned.khi_solver(n).compute_dt(u0)[0].item()
+    nsteps = int(round(2.0 / h))
+    net = crk.MLP.load(WEIGHTS)
+    res = {}
+    for kind in ("none", "modal", "mlp"):
+        s = learned.khi_solver(n, limiter=kind != "none")
+        if kind == "mlp":
+            net.bind(s)
+        u = [u0.clone(), s.new_state()]
+        dtt = torch.tensor([h, 0.0], dtype=torch.float64, device="cuda")
+        asum = 0.0
+        for k in range(nsteps):
+            s.step(u[k % 2], u[(k + 1) % 2], dtt, compute_dt=False)
+            if kind != "none" and k % 50 == 0:
+                asum += float(s.indicator(u[(k + 1) % 2])[1].sum())
+        rc, fb, _ = s.check(u[nsteps % 2])
+        assert rc == crk.OK, kind
+        res[kind] = (u[nsteps % 2].cpu().numpy(), asum)
+    ref = res["none"][0]
+    err = {k: float(np.sqrt(np.sum((res[k][0] - ref) ** 2) / np.sum(ref ** 2))) for k in ("modal", "mlp")}
+    print(f"t = 2 ({nsteps} steps): rel L2 to the unlimited run: modal {err['modal']:.3e}, network {err['mlp']:.3e}; "
+          f"sum alpha: modal {res['modal'][1]:.2f}, network {res['mlp'][1]:.2f}")
+    assert err["mlp"] < err["modal"]
+    assert res["mlp"][1] < res["modal"][1]
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
 def test_pipelined_learned_tile_flags(orc):
     """Pipelined steps with the trained network bound, where the network's
     own coefficients flag the local-phase tiles that may blend, against
