@@ -139,16 +139,19 @@ struct crk_solver {
 
 namespace {
 
-// Tile flags (pipelined step with the limiter, 2D, Kennedy-Gruber flux;
-// the learned indicator flags from its own coefficients as well): flagged-clear tiles take the local-phase instance without the
+// Tile flags (pipelined step with the limiter, 2D, Kennedy-Gruber or
+// Ranocha flux; the learned indicator flags from its own coefficients as
+// well): flagged-clear tiles take the local-phase instance without the
 // blending code, whose register count allows a fourth wavefront per SIMD in
-// FP64 (120 instead of 156 VGPRs) and a seventh in FP32; with the Ranocha
-// flux it stays at three in FP64 and the second launch would cost more than
-// it saves.  A 1D mesh small enough for crk_run's single launch keeps the
-// blending instance so that both give the same bits.
+// FP64 with Kennedy-Gruber (120 instead of 156 VGPRs) and a seventh in FP32;
+// with the Ranocha flux it stays at three wavefronts in FP64 but issues 6 %
+// fewer instructions (77 instead of 83 us on the 256^2 KHI state), a little
+// more than the nearly empty second launch costs.  A 1D mesh small enough
+// for crk_run's single launch keeps the blending instance so that both give
+// the same bits.
 bool use_tile_flags(const crk_solver *s)
 {
-    return s->limiter == CRK_LIM_BLEND && s->mesh.dim == 2 && s->flux == CRK_VOL_KG;
+    return s->limiter == CRK_LIM_BLEND && s->mesh.dim == 2 && (s->flux == CRK_VOL_KG || s->flux == CRK_VOL_RANOCHA);
 }
 
 template <class F>
