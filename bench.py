@@ -9,10 +9,14 @@ final update + CFL time-step reduction + blending indicator of the new state
 (the pipelined step; crk_prepare seeds dt and the indicator of u0), with the
 state resident in HBM.  Metric: DOF-updates/s (one DOF = one solution node).
 
-The same JSON line carries the variants (FP32; the batch of 512 uneven
-problems replayed as a HIP graph; Kelvin-Helmholtz 512^2 with the learned
-indicator; GLM-MHD Orszag-Tang; the 1D density wave), each with its relative
-L2 error against the FP64 CPU oracle stepped from the same initial state.
+The same JSON line carries the variants (FP32; the Ranocha EC flux; rough
+states that blend everywhere or on one half; the batch of 512 uneven problems
+replayed as a HIP graph; Kelvin-Helmholtz 512^2 with the learned indicator;
+GLM-MHD Orszag-Tang in FP64 and FP32 and with the stage-wise non-conservative
+interface flux; the 1D density wave; cRKFR against the standard multi-stage
+RKFR step; the Kelvin-Helmholtz and Richtmyer-Meshkov robustness runs), each
+throughput variant with its relative L2 error against the FP64 CPU oracle
+stepped from the same initial state.
 ``--gpus`` above 1 is rejected: the path is measured on a single GPU (it is not sharded).
 """
 from __future__ import annotations
