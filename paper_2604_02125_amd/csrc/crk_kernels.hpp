@@ -33,6 +33,16 @@ inline int tile_block_rt(int np) { return 64 % np == 0 ? CRK_WAVE_TILE : BLOCK; 
 // tiles) keeps horizontally adjacent element tiles, which share the cache
 // lines of their face data, on one XCD and close in time.  A bijection of
 // [0, G) for every G.
+// Tiles per workgroup of the two local-phase instances (single-wavefront
+// tiles): the instance with the blending code, which skips every tile that
+// cannot blend, runs several per workgroup.
+#ifndef CRK_LOCAL_WPB_PLAIN
+#define CRK_LOCAL_WPB_PLAIN 1
+#endif
+#ifndef CRK_LOCAL_WPB_BLEND
+#define CRK_LOCAL_WPB_BLEND 4
+#endif
+
 constexpr int NXCD = 8;
 __device__ __forceinline__ long xcd_tile(long b, long G)
 {
@@ -811,23 +821,38 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 
 // With tile flags, the BLEND = false instance runs the clear tiles (and
 // clears every tile's flag of the next step) and the BLEND = true instance,
-// launched after it, the flagged ones; a workgroup leaves at once on a tile
-// of the other kind.
-template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB = 0, bool BLEND = true, bool NCS = false>
-__global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 1>()) k_local(const Tables t, const StepPtrs a)
+// launched after it, the flagged ones; a tile of the other kind is left at
+// once.  WPB > 1 (single-wavefront tiles only): each workgroup holds WPB
+// wavefronts, each running its own tile with its own LDS slice and never
+// waiting for the others, so a launch that skips most tiles dispatches WPB
+// times fewer workgroups.
+template <int NP, int WPB>
+constexpr int local_wpb() { return tile_block<NP>() == 64 ? WPB : 1; }
+
+template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB = 0, bool BLEND = true, bool NCS = false,
+          int WPB = 1>
+__global__ void __launch_bounds__(tile_block<DIM == 2 ? (N + 1) * (N + 1) : N + 1>() * WPB)
+k_local(const Tables t, const StepPtrs a)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     constexpr int TB = tile_block<NP>();
-    __shared__ real smem[LocalShape<real, EQ, DIM, N, FLUX>::slots * TB];
-    const int tile = xcd_chunk_tile(blockIdx.x, gridDim.x);
+    constexpr int SL = LocalShape<real, EQ, DIM, N, FLUX>::slots * TB;
+    static_assert(WPB == 1 || TB == 64, "several tiles per workgroup need single-wavefront tiles");
+    __shared__ real smem[SL * WPB];
+    const int w = WPB == 1 ? 0 : (int)(threadIdx.x / 64);
+    const long tile = (long)xcd_chunk_tile(blockIdx.x, gridDim.x) * WPB + w;
+    if constexpr (WPB > 1) {
+        if (tile * (TB / NP) >= t.nelem) return;
+    }
     if (a.tiles_in != nullptr) {
         const int flagged = a.tiles_in[tile];
         if constexpr (!BLEND) {
-            if (threadIdx.x == 0) a.tiles_out[tile] = 0;
+            if (threadIdx.x % 64 == 0) a.tiles_out[tile] = 0;
         }
         if (BLEND ? flagged == 0 : flagged != 0) return;
     }
-    local_tile<real, EQ, DIM, N, FLUX, S, TB, TAB, BLEND, NCS>(t, a, (long)tile * (TB / NP), smem);
+    local_tile<real, EQ, DIM, N, FLUX, S, TB, TAB, BLEND, NCS>(t, a, tile * (TB / NP), smem + w * SL,
+                                                               WPB == 1 ? -1 : (int)(threadIdx.x % 64));
 }
 
 // ---------------------------------------------------------------- K8 helper: modal indicator
@@ -1457,21 +1482,25 @@ hipError_t launch_local(const Tables &t, const StepPtrs &p, hipStream_t s)
     constexpr int TB = tile_block<NP>();
     constexpr int EPB = TB / NP;
     const int grid = (t.nelem + EPB - 1) / EPB;
-#define CRK_LOCAL_LAUNCH(BL)                                                                                       \
-    switch (t.stages) {                                                                                            \
-    case 1: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 1, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p); break; \
-    case 2: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 2, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p); break; \
-    case 3: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 3, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p); break; \
-    case 4:                                                                                                        \
-        if (t.tableau == 1) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 1, BL>), dim3(grid), dim3(TB), 0, s, t, p); \
-        else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p);  \
-        break;                                                                                                     \
-    case 5: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 5, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p); break; \
-    case 6:                                                                                                        \
-        if (t.tableau == 2) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6, 2, BL>), dim3(grid), dim3(TB), 0, s, t, p); \
-        else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6, 0, BL>), dim3(grid), dim3(TB), 0, s, t, p);  \
-        break;                                                                                                     \
-    default: return hipErrorInvalidValue;                                                                          \
+    constexpr int WP = local_wpb<NP, CRK_LOCAL_WPB_PLAIN>(), WB = local_wpb<NP, CRK_LOCAL_WPB_BLEND>();
+#define CRK_LOCAL_LAUNCH(BL, W)                                                                                    \
+    {                                                                                                              \
+        const dim3 g((grid + W - 1) / W), b(TB * W);                                                               \
+        switch (t.stages) {                                                                                        \
+        case 1: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 1, 0, BL, false, W>), g, b, 0, s, t, p); break; \
+        case 2: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 2, 0, BL, false, W>), g, b, 0, s, t, p); break; \
+        case 3: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 3, 0, BL, false, W>), g, b, 0, s, t, p); break; \
+        case 4:                                                                                                    \
+            if (t.tableau == 1) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 1, BL, false, W>), g, b, 0, s, t, p); \
+            else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 4, 0, BL, false, W>), g, b, 0, s, t, p);  \
+            break;                                                                                                 \
+        case 5: hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 5, 0, BL, false, W>), g, b, 0, s, t, p); break; \
+        case 6:                                                                                                    \
+            if (t.tableau == 2) hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6, 2, BL, false, W>), g, b, 0, s, t, p); \
+            else hipLaunchKernelGGL((k_local<real, EQ, DIM, N, FLUX, 6, 0, BL, false, W>), g, b, 0, s, t, p);  \
+            break;                                                                                                 \
+        default: return hipErrorInvalidValue;                                                                      \
+        }                                                                                                          \
     }
     // without blending coefficients (no limiter) every tile takes the
     // instance without the blending code; with tile flags both run, the
@@ -1492,13 +1521,13 @@ hipError_t launch_local(const Tables &t, const StepPtrs &p, hipStream_t s)
     const bool blend = p.alpha != nullptr || p.alpha_raw != nullptr;
     const int which = p.instances ? p.instances : 3;
     if ((which & 1) && (!blend || p.tiles_in != nullptr)) {
-        CRK_LOCAL_LAUNCH(false)
+        CRK_LOCAL_LAUNCH(false, WP)
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if constexpr (EQ == EQ_EULER) {
         if ((which & 2) && blend) {
-            CRK_LOCAL_LAUNCH(true)
+            CRK_LOCAL_LAUNCH(true, WB)
         }
     }
 #undef CRK_LOCAL_LAUNCH

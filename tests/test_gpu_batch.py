@@ -56,6 +56,38 @@ def test_batch_matches_oracle_per_problem(orc, tuning):
         assert abs(b.dt[2 * i].item() - orc.compute_dt(p, ref)) <= 1e-14 * b.dt[2 * i].item()
 
 
+EDGE_SPECS = {
+    "one_element_deg3": [(1, 3)],
+    "deg4_only_tiny": [(1, 4), (2, 4)],
+    "deg4_only": [(6, 4), (3, 4)],
+    "deg3_only": [(5, 3)],
+    "mixed_tiny": [(2, 3), (1, 4)],
+}
+
+
+@pytest.mark.parametrize("tuning", [(128, 0, 0), (64, 2, 0), (128, 0, 1)], ids=["tile", "persistent", "merged"])
+@pytest.mark.parametrize("case", sorted(EDGE_SPECS))
+def test_batch_edge_shapes(orc, case, tuning):
+    """Batches with a single degree (the other degree's launch has no
+    tiles), single-element problems (every neighbour is the element itself)
+    and fewer tiles than a persistent grid, in every launch shape."""
+    specs = EDGE_SPECS[case]
+    b = crk.Batch(specs, tuning=tuning)
+    u0 = _fill(orc, b, seed=5)
+    with torch.cuda.stream(b.stream):
+        b.prepare(0)
+        b.advance(0)
+        b.advance(1)
+    b.stream.synchronize()
+    for i, (n, N) in enumerate(specs):
+        p = orc.Problem(dim=2, nx=n, ny=n, N=N, vol_flux=orc.VOL_RANOCHA)
+        ref = u0[i]
+        for _ in range(2):
+            ref, _ = orc.crk_step(p, ref, orc.compute_dt(p, ref))
+        assert _rel(b.view(0, i).cpu().numpy(), ref) <= 1e-12, (case, i)
+        assert abs(b.dt[2 * i].item() - orc.compute_dt(p, ref)) <= 1e-14 * b.dt[2 * i].item()
+
+
 def test_batch_equals_single_problem_runs(orc):
     b = crk.Batch(SPECS)
     u0 = _fill(orc, b, seed=2)
@@ -119,6 +151,8 @@ def test_batch_fp32(orc):
 
 
 def test_batch_rejects_bad_input():
+    with pytest.raises(crk.CrkError):
+        crk.Batch([])                 # no problems
     with pytest.raises(crk.CrkError):
         crk.Batch([(4, 2)])           # degree 2 not in a batch
     with pytest.raises(crk.CrkError):
