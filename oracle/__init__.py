@@ -167,6 +167,7 @@ def lib():
             "orc_compute_ch": (C.c_double, [P, _dp]),
             "orc_compute_dt": (C.c_double, [P, _dp]),
             "orc_indicator": (C.c_int, [P, _dp, _dp, _dp, _dp]),
+            "orc_smooth_alpha": (None, [P, _dp, _dp]),
             "orc_crk_step": (C.c_int, [P, _dp, C.c_double, _dp, _dp, _dp]),
             "orc_local_phase": (C.c_int, [P, _dp, C.c_double, _dp, _dp, _dp, _dp]),
             "orc_face_fluxes": (C.c_int, [P, _dp, C.c_double, _dp, _dp]),
@@ -299,6 +300,16 @@ def indicator(prob: Problem, u):
     araw, a, feat = np.zeros(E), np.zeros(E), np.zeros((E, prob.nnode))
     lib().orc_indicator(C.byref(prob.to_c()), _ptr(u), _ptr(araw), _ptr(a), _ptr(feat))
     return araw, a, feat
+
+
+def smooth_alpha(prob: Problem, alpha_raw):
+    """alpha_e = max(alpha_raw_e, max over face neighbours of alpha_raw / 2)."""
+    araw = np.ascontiguousarray(alpha_raw, dtype=np.float64)
+    if araw.shape != (prob.nelem,):
+        raise ValueError("one coefficient per element")
+    a = np.zeros(prob.nelem)
+    lib().orc_smooth_alpha(C.byref(prob.to_c()), _ptr(araw), _ptr(a))
+    return a
 
 
 def crk_step(prob: Problem, u, dt: float, alpha=None):

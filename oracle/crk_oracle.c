@@ -642,21 +642,13 @@ static double indicator_element(const orc_problem *P, const refel_t *r, const do
     return a;
 }
 
-/* alpha_raw[e] (clipped, capped) and alpha[e] after smoothing
- * alpha_e <- max(alpha_e, max over face neighbours of alpha_nb / 2). */
-int orc_indicator(const orc_problem *P, const double *u, double *alpha_raw, double *alpha, double *features)
+/* Smoothing of the blending coefficients over face neighbours:
+ * alpha_e <- max(alpha_e, max over face neighbours of alpha_nb / 2)
+ * (beyond a wall the neighbour is the element's mirror image, whose
+ * coefficient is its own). */
+void orc_smooth_alpha(const orc_problem *P, const double *alpha_raw, double *alpha)
 {
-    refel_t r;
-    make_refel(P, &r);
     long E = nelem_of(P);
-    int np = r.np, M = r.M;
-#pragma omp parallel for num_threads(nthreads_of(P)) schedule(static)
-    for (long e = 0; e < E; ++e) {
-        double ue[ORC_MAXNP * ORC_MAXM];
-        gather_elem(P, u, e, ue);
-        alpha_raw[e] = indicator_element(P, &r, ue, features ? features + e * np : NULL);
-    }
-    (void)M;
     for (long e = 0; e < E; ++e) {
         double a = alpha_raw[e];
         for (int d = 0; d < P->dim; ++d)
@@ -666,6 +658,22 @@ int orc_indicator(const orc_problem *P, const double *u, double *alpha_raw, doub
             }
         alpha[e] = a;
     }
+}
+
+/* alpha_raw[e] (clipped, capped) and alpha[e] after smoothing. */
+int orc_indicator(const orc_problem *P, const double *u, double *alpha_raw, double *alpha, double *features)
+{
+    refel_t r;
+    make_refel(P, &r);
+    long E = nelem_of(P);
+    int np = r.np;
+#pragma omp parallel for num_threads(nthreads_of(P)) schedule(static)
+    for (long e = 0; e < E; ++e) {
+        double ue[ORC_MAXNP * ORC_MAXM];
+        gather_elem(P, u, e, ue);
+        alpha_raw[e] = indicator_element(P, &r, ue, features ? features + e * np : NULL);
+    }
+    orc_smooth_alpha(P, alpha_raw, alpha);
     return 0;
 }
 

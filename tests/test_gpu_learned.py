@@ -263,3 +263,64 @@ def test_pipelined_learned_tile_flags(orc):
     rel = max(np.max(np.abs(got[v] - ref[v])) / np.max(np.abs(ref[v])) for v in range(ref.shape[0]))
     print(f"pipelined vs crk_step with the network: {rel:.2e}")
     assert rel <= 1e-13
+
+
+def _oracle_learned_alpha(orc, p, u, th, lo, hi):
+    """The learned blending coefficients composed from the oracle's parts:
+    modal energy fractions -> log features -> the FP64 network with the
+    BF16-rounded parameters -> alpha_max sigmoid, cut below alpha_min, where
+    every feature lies in the training range [lo, hi] (compared in FP32, as
+    the features are stored), else the modal coefficient; then smoothing over
+    face neighbours.  Also returns the network's uncut coefficient."""
+    araw_modal, _, fo = orc.indicator(p, u)
+    x32 = orc.feature_transform(fo).astype(np.float32)
+    z, a = orc.mlp_forward(16, 64, th, x32.astype(np.float64), p.alpha_max)
+    inside = np.all((x32 >= lo) & (x32 <= hi), axis=1) & np.isfinite(z)
+    araw = np.where(inside, np.where(a < p.alpha_min, 0.0, a), araw_modal)
+    return araw, orc.smooth_alpha(p, araw), a, inside
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights not present")
+@pytest.mark.parametrize("fallback", [False, True], ids=["trained_range", "narrowed_range"])
+def test_pipelined_learned_step_against_oracle(orc, fallback):
+    """End to end: one pipelined step with the trained network bound (the
+    features of u^n from the interface tail of crk_prepare, inference on the
+    matrix cores, smoothing and tile flags in the local phase) against the
+    oracle's step with the coefficients composed from the oracle's own
+    indicator, network and smoothing.  The network runs in FP32 on the GPU
+    and in FP64 in the oracle, so the coefficients agree to ~1e-8; the input
+    is checked to have no element within 1e-7 of the alpha_min cut, where
+    the two could decide differently.  narrowed_range: the first feature's
+    range is cut at its 70th percentile, so that a third of the elements
+    fall back to the modal coefficient."""
+    p, s, u = _khi_pair(orc, n=32)
+    pg = orc.Problem(dim=2, nx=32, ny=32, x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, N=3, vol_flux=orc.VOL_KG,
+                     limiter=orc.LIM_BLEND_GIVEN)
+    net = crk.MLP.load(WEIGHTS)
+    th = _bf16_round(net.theta.cpu().numpy())
+    lo, hi = net.lo.cpu().numpy().copy(), net.hi.cpu().numpy().copy()
+    if fallback:
+        _, _, fo = orc.indicator(p, u)
+        hi[0] = np.float32(np.quantile(orc.feature_transform(fo)[:, 0], 0.7))
+        net.hi = torch.tensor(hi, device="cuda")
+    net.bind(s)
+    araw, alpha, a_net, inside = _oracle_learned_alpha(orc, p, u, th, lo, hi)
+    assert np.min(np.abs(a_net[inside] - p.alpha_min)) > 1e-7
+    assert (araw[inside] > 0).sum() > 50
+    assert (not fallback) or (0 < (~inside).sum() < p.nelem)
+    ug = torch.tensor(u, device="cuda")
+    ga, gs = s.indicator(ug)
+    assert np.max(np.abs(ga.cpu().numpy() - araw)) <= 1e-7
+    assert np.max(np.abs(gs.cpu().numpy() - alpha)) <= 1e-7
+    dt = orc.compute_dt(p, u)
+    ref, _ = orc.crk_step(pg, u, dt, alpha)
+    buf, dtg = [ug.clone(), s.new_state()], s.new_dt()
+    s.prepare(buf[0], dtg)
+    assert abs(dtg[0].item() - dt) <= 1e-14 * dt
+    s.advance(buf[0], buf[1], dtg)
+    torch.cuda.synchronize()
+    got = buf[1].cpu().numpy()
+    rel = max(np.max(np.abs(got[v] - ref[v])) / np.max(np.abs(ref[v])) for v in range(ref.shape[0]))
+    print(f"learned step against the oracle ({'narrowed' if fallback else 'trained'} range): {rel:.2e}, "
+          f"{int((araw > 0).sum())} elements with alpha > 0, {int((~inside).sum())} on the modal fallback")
+    assert rel <= 1e-8

@@ -469,6 +469,31 @@ def test_indicator_smoothing(orc):
     nb = np.maximum.reduce([np.roll(A, 1, 0), np.roll(A, -1, 0), np.roll(A, 1, 1), np.roll(A, -1, 1)])
     assert np.array_equal(a.reshape(8, 8), np.maximum(A, 0.5 * nb))
     assert araw.max() == prob.alpha_max
+    # the standalone smoothing (used where the raw coefficients come from
+    # elsewhere, e.g. a learned indicator) is the same rule
+    assert np.array_equal(orc.smooth_alpha(prob, araw), a)
+
+
+def test_smoothing_of_given_coefficients(orc):
+    """One positive coefficient spreads half its value to the four face
+    neighbours (across the periodic wrap), not to diagonal neighbours; a
+    larger own value is kept; beyond a wall the element is its own
+    neighbour."""
+    prob = orc.Problem(dim=2, N=3, nx=5, ny=4)
+    araw = np.zeros(20)
+    araw[0] = 0.4                 # element (0, 0): neighbours (1, 0), (4, 0), (0, 1), (0, 3)
+    araw[7] = 0.3                 # element (2, 1) keeps its own value
+    a = orc.smooth_alpha(prob, araw).reshape(4, 5)
+    expect = np.zeros((4, 5))
+    expect[0, 0] = 0.4
+    expect[0, 1] = expect[0, 4] = expect[1, 0] = expect[3, 0] = 0.2
+    expect[1, 2] = 0.3
+    expect[0, 2] = expect[2, 2] = expect[1, 1] = expect[1, 3] = 0.15
+    assert np.array_equal(a, expect)
+    walled = orc.Problem(dim=2, N=3, nx=5, ny=4, bc=(orc.BC_WALL, orc.BC_WALL))
+    w = orc.smooth_alpha(walled, araw).reshape(4, 5)
+    assert w[0, 4] == 0.0 and w[3, 0] == 0.0          # no wrap across walls
+    assert w[0, 1] == 0.2 and w[1, 0] == 0.2
 
 
 def test_diagnostics(orc):
