@@ -48,13 +48,15 @@ struct BatchTile {
 // degree-4 path's register budget for every tile).
 template <typename real, int FLUX, int NDEG>
 struct BatchLocalLds {
-    static constexpr int s3 = LocalShape<real, EQ_EULER, 2, 3, FLUX>::slots;
-    static constexpr int s4 = LocalShape<real, EQ_EULER, 2, 4, FLUX>::slots;
+    static constexpr int s3 = LocalShape<real, EQ_EULER, 2, 3, FLUX, false>::slots;
+    static constexpr int s4 = LocalShape<real, EQ_EULER, 2, 4, FLUX, false>::slots;
     static constexpr int slots = NDEG == 3 ? s3 : (NDEG == 4 ? s4 : (s3 > s4 ? s3 : s4));
 };
 
+// (three wavefronts per SIMD: the FP64 degree-4 path then holds 168
+// registers, spilling a few, which beats two wavefronts)
 template <typename real, int FLUX, int BLK, int NDEG, bool PERSIST>
-__global__ void __launch_bounds__(BLK) k_batch_local(const BatchProblem *probs, const BatchTile *tiles, int t0, int t1,
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(3))) k_batch_local(const BatchProblem *probs, const BatchTile *tiles, int t0, int t1,
                                                      int dir)
 {
     __shared__ real smem[BatchLocalLds<real, FLUX, NDEG>::slots * BLK];

@@ -305,8 +305,9 @@ __device__ __forceinline__ void element_sync()
     }
 }
 
-// LDS slots (of BLK values each) used by the local-stage tile
-template <typename real, int EQ, int DIM, int N, int FLUX>
+// LDS slots (of BLK values each) used by the local-stage tile (BL: the
+// instance with the blending code)
+template <typename real, int EQ, int DIM, int N, int FLUX, bool BL = true>
 struct LocalShape {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
     static constexpr int n1 = N + 1;
@@ -320,7 +321,7 @@ struct LocalShape {
     // face neighbours ((2 DIM + 1) values per element of NP lanes), DIM slots
     // the Rusanov speed of the faces through each node
     static constexpr int NP = DIM == 2 ? n1 * n1 : n1;
-    static constexpr int ASL = (2 * DIM + 1 + NP - 1) / NP;
+    static constexpr int ASL = BL ? (2 * DIM + 1 + NP - 1) / NP : 0;
     // Euler, whole elements per wavefront: one slot for the sound speed of
     // u^n, shared by the subcell fluxes of the blending limiter
     static constexpr int CS = (EQ == EQ_EULER && 64 % NP == 0) ? 1 : 0;
@@ -333,13 +334,18 @@ struct LocalShape {
     // the exchange cost as much as the pair.)
     static constexpr bool BAL = DIM == 2 && SYM && KSELF > 0 && EQ == EQ_EULER && FLUX == VOL_RANOCHA;
     static constexpr int XB = BAL ? Phys::M : 0;
-    // degree 4 in 2D (256-lane workgroups, workgroup barriers): the node
-    // fields alternate between two sets of slots from stage to stage, so that
-    // a stage may overwrite them without waiting for the previous stage's
-    // readers (one barrier fewer per stage; the LDS this adds does not lower
-    // the occupancy of these register-bound kernels)
-    static constexpr bool DBF = DIM == 2 && N == 4;
-    static constexpr int slots = (DBF ? 2 : 1) * Phys::NF + NX + ASL + DIM + CS + XB;
+    // Degree 4 in 2D (workgroup barriers).  FP64 Euler: the coefficients
+    // 2 D_{p,q}/dx_d of the lane's rotations and diagonal come from a table
+    // in LDS (one slot) instead of 2 (N+1) registers each, so that three
+    // wavefronts per SIMD fit in registers and LDS.  Otherwise (MHD, bound
+    // at one wavefront by its registers; FP32, not register-bound) the node
+    // fields alternate between two sets of slots from stage to stage, so
+    // that a stage may overwrite them without waiting for the previous
+    // stage's readers (one barrier fewer per stage).
+    static constexpr bool DTAB = DIM == 2 && N == 4 && EQ == EQ_EULER && sizeof(real) == 8;
+    static constexpr bool DBF = DIM == 2 && N == 4 && !DTAB;
+    static constexpr int DT = DTAB ? 1 : 0;
+    static constexpr int slots = (DBF ? 2 : 1) * Phys::NF + NX + ASL + DIM + CS + XB + DT;
 };
 
 // One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
@@ -354,7 +360,7 @@ template <typename real, int EQ, int DIM, int N, int FLUX, int S, int BLK, int T
 __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, long e0, real *smem, int lane = -1)
 {
     using Phys = typename PhysOf<real, EQ, DIM, FLUX>::type;
-    using Shape = LocalShape<real, EQ, DIM, N, FLUX>;
+    using Shape = LocalShape<real, EQ, DIM, N, FLUX, BLEND>;
     constexpr int n1 = N + 1;
     constexpr int NP = DIM == 2 ? n1 * n1 : n1;
     constexpr int EPB = BLK / NP;
@@ -370,7 +376,10 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     real *llds = alds + Shape::ASL * BLK; // [DIM][BLK]
     real *clds = llds + DIM * BLK;        // [CS][BLK]
     real *xb = clds + Shape::CS * BLK;    // [XB][BLK]
+    real *dtab = xb + Shape::XB * BLK;    // DTAB: [DIM][N+1][N+1], dtab[(d n1 + r) n1 + k] = 2 D_{r,(r+k) mod n1}/dx_d
     constexpr bool CSH = Shape::CS > 0;
+    constexpr bool DTAB = Shape::DTAB;
+    static_assert(!DTAB || DIM * (N + 1) * (N + 1) <= BLK, "the coefficient table fits one slot");
     constexpr bool BAL = Shape::BAL;
     constexpr int NA = 2 * DIM + 1;
 
@@ -395,14 +404,29 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         const int r = pd[d];
+        if constexpr (!DTAB) {
 #pragma unroll
-        for (int k = 1; k <= N; ++k) {
-            const int q = r + k < n1 ? r + k : r + k - n1;
-            Dk[d][k - 1] = real(2.0 * t.D[r][q] * t.invdx[d]);
+            for (int k = 1; k <= N; ++k) {
+                const int q = r + k < n1 ? r + k : r + k - n1;
+                Dk[d][k - 1] = real(2.0 * t.D[r][q] * t.invdx[d]);
+            }
+            Ddiag[d] = real(2.0 * t.D[r][r] * t.invdx[d]);
         }
-        Ddiag[d] = real(2.0 * t.D[r][r] * t.invdx[d]);
         invw[d] = real(t.invw_dx[d][r]);
     }
+    if constexpr (DTAB) {
+        // visible to every lane after the first stage's barrier
+        if (tid < DIM * n1 * n1) {
+            const int d = tid / (n1 * n1), r = (tid / n1) % n1, k = tid % n1;
+            const int q = r + k < n1 ? r + k : r + k - n1;
+            dtab[tid] = real(2.0 * t.D[r][q] * t.invdx[d]);
+        }
+    }
+    // 2 D_{p,q}/dx_d of rotation k = 1..N (k = 0: the diagonal)
+    auto dk = [&](int d, int k) -> real {
+        if constexpr (DTAB) return dtab[(d * n1 + pd[d]) * n1 + k];
+        else return k == 0 ? Ddiag[d] : Dk[d][k - 1];
+    };
     // MHD: plain D_pq / dx_d for the non-conservative term, all q
     real Dn[DIM][n1];
     if constexpr (EQ == EQ_MHD) {
@@ -634,8 +658,9 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                 for (int f = 0; f < NF; ++f) ndq[f] = lds[f * BLK + base + q];
                 real fs[M];
                 Phys::pair(d, nd, ndq, fs, ctx);
+                const real ck = dk(d, k);
 #pragma unroll
-                for (int v = 0; v < M; ++v) R[v] += Dk[d][k - 1] * fs[v];
+                for (int v = 0; v < M; ++v) R[v] += ck * fs[v];
                 if constexpr (SYM) {
                     if (k <= NPRIM) {
 #pragma unroll
@@ -649,10 +674,10 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                 real fp[M];
                 if constexpr (EQ == EQ_EULER) Phys::phys_cons(d, us, nd, fp, ctx);
                 else Phys::phys(d, nd, fp, ctx);
-                const real gp = bi * oafh[d], gw = bi * cF[d];
+                const real gp = bi * oafh[d], gw = bi * cF[d], c0 = dk(d, 0);
 #pragma unroll
                 for (int v = 0; v < M; ++v) {
-                    R[v] += Ddiag[d] * fp[v];
+                    R[v] += c0 * fp[v];
                     P[d][v] += gp * fp[v];
                     W[v] -= gw * fp[v];
                 }
@@ -735,7 +760,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 #pragma unroll
             for (int f = 0; f < NF; ++f) ndq[f] = lds[f * BLK + base + q];
             Phys::pair_rt(xm ? 0 : 1, nd, ndq, fs, ctx);
-            const real c = xm ? Dk[0][KSELF - 1] : Dk[DIM - 1][KSELF - 1];
+            const real c = xm ? dk(0, KSELF) : dk(DIM - 1, KSELF);
 #pragma unroll
             for (int v = 0; v < M; ++v) {
                 R[v] += c * fs[v];
@@ -747,7 +772,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
             if constexpr (BAL) {
                 // the pair of the other direction, from the lane that evaluated it
                 const int src = base + (xm ? line_node<N, DIM>(pd, 1, qy) : line_node<N, DIM>(pd, 0, qx));
-                const real c = xm ? Dk[DIM - 1][KSELF - 1] : Dk[0][KSELF - 1];
+                const real c = xm ? dk(DIM - 1, KSELF) : dk(0, KSELF);
 #pragma unroll
                 for (int v = 0; v < M; ++v) R[v] += c * xb[v * BLK + src];
             }
@@ -759,7 +784,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                     int sd = pd[d] - k;
                     if (sd < 0) sd += n1;
                     const int src = base + line_node<N, DIM>(pd, d, sd);
-                    const real c = Dk[d][n1 - k - 1];
+                    const real c = dk(d, n1 - k);
 #pragma unroll
                     for (int v = 0; v < M; ++v) R[v] += c * xch[((d * NPRIM + (k - 1)) * M + v) * BLK + src];
                 }
@@ -836,7 +861,7 @@ k_local(const Tables t, const StepPtrs a)
 {
     constexpr int NP = DIM == 2 ? (N + 1) * (N + 1) : N + 1;
     constexpr int TB = tile_block<NP>();
-    constexpr int SL = LocalShape<real, EQ, DIM, N, FLUX>::slots * TB;
+    constexpr int SL = LocalShape<real, EQ, DIM, N, FLUX, BLEND>::slots * TB;
     static_assert(WPB == 1 || TB == 64, "several tiles per workgroup need single-wavefront tiles");
     __shared__ real smem[SL * WPB];
     const int w = WPB == 1 ? 0 : (int)(threadIdx.x / 64);
@@ -1224,7 +1249,7 @@ constexpr int RUN_BLOCK = 256;   // one wavefront per SIMD: no register cap
 template <typename real, int EQ, int DIM, int N, int FLUX, int S, int TAB, bool BLEND>
 __global__ void __launch_bounds__(RUN_BLOCK) k_run(const Tables t, const StepPtrs a0, double *dt_io, int nsteps)
 {
-    constexpr size_t LB = (size_t)LocalShape<real, EQ, DIM, N, FLUX>::slots * RUN_BLOCK * sizeof(real);
+    constexpr size_t LB = (size_t)LocalShape<real, EQ, DIM, N, FLUX, BLEND>::slots * RUN_BLOCK * sizeof(real);
     constexpr size_t DB = (size_t)5 * RUN_BLOCK * sizeof(double);
     __shared__ double pool[(LB > DB ? LB : DB) / sizeof(double)];   // local phase, then interface phase
     __shared__ double dtl[2];
