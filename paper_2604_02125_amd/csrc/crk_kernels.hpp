@@ -318,13 +318,13 @@ struct LocalShape {
     static constexpr int KSELF = (SYM && n1 % 2 == 0) ? n1 / 2 : 0;  // self-mirrored rotation, evaluated directly
     static constexpr int NX = SYM ? DIM * NPRIM * Phys::M : 0;
     // ASL slots carry the blending coefficients of each element and of its
-    // face neighbours ((2 DIM + 1) values per element of NP lanes), DIM slots
-    // the Rusanov speed of the faces through each node
+    // face neighbours ((2 DIM + 1) values per element of NP lanes; only in
+    // the instance with the blending code)
     static constexpr int NP = DIM == 2 ? n1 * n1 : n1;
     static constexpr int ASL = BL ? (2 * DIM + 1 + NP - 1) / NP : 0;
-    // Euler, whole elements per wavefront: one slot for the sound speed of
-    // u^n, shared by the subcell fluxes of the blending limiter
-    static constexpr int CS = (EQ == EQ_EULER && 64 % NP == 0) ? 1 : 0;
+    // Euler, whole elements per wavefront, instance with the blending code:
+    // one slot for the sound speed of u^n, shared by the subcell fluxes
+    static constexpr int CS = (BL && EQ == EQ_EULER && 64 % NP == 0) ? 1 : 0;
     // 2D, N+1 even: the pairs of the self-mirrored rotation (p, p + (N+1)/2)
     // along x and along y are as many as the nodes.  With the Ranocha flux
     // each lane evaluates one of them (the x pair when exactly one of its
@@ -334,18 +334,20 @@ struct LocalShape {
     // the exchange cost as much as the pair.)
     static constexpr bool BAL = DIM == 2 && SYM && KSELF > 0 && EQ == EQ_EULER && FLUX == VOL_RANOCHA;
     static constexpr int XB = BAL ? Phys::M : 0;
-    // Degree 4 in 2D (workgroup barriers).  FP64 Euler: the coefficients
-    // 2 D_{p,q}/dx_d of the lane's rotations and diagonal come from a table
-    // in LDS (one slot) instead of 2 (N+1) registers each, so that three
-    // wavefronts per SIMD fit in registers and LDS.  Otherwise (MHD, bound
-    // at one wavefront by its registers; FP32, not register-bound) the node
-    // fields alternate between two sets of slots from stage to stage, so
-    // that a stage may overwrite them without waiting for the previous
+    // FP64 Euler in 2D, degree 4, and degree 3 with the Ranocha flux: the
+    // coefficients 2 D_{p,q}/dx_d of the lane's rotations and diagonal come
+    // from a table in LDS (one slot) instead of 2 (N+1) registers each, so
+    // that one more wavefront per SIMD fits in registers and LDS (three at
+    // degree 4, four for Ranocha at degree 3).  Otherwise at degree 4 (MHD,
+    // bound at one wavefront by its registers; FP32, not register-bound) the
+    // node fields alternate between two sets of slots from stage to stage,
+    // so that a stage may overwrite them without waiting for the previous
     // stage's readers (one barrier fewer per stage).
-    static constexpr bool DTAB = DIM == 2 && N == 4 && EQ == EQ_EULER && sizeof(real) == 8;
+    static constexpr bool DTAB = DIM == 2 && EQ == EQ_EULER && sizeof(real) == 8 &&
+                                 (N == 4 || (N == 3 && FLUX == VOL_RANOCHA));
     static constexpr bool DBF = DIM == 2 && N == 4 && !DTAB;
     static constexpr int DT = DTAB ? 1 : 0;
-    static constexpr int slots = (DBF ? 2 : 1) * Phys::NF + NX + ASL + DIM + CS + XB + DT;
+    static constexpr int slots = (DBF ? 2 : 1) * Phys::NF + NX + ASL + CS + XB + DT;
 };
 
 // One tile of BLK lanes: elements e0 .. e0 + BLK/(N+1)^DIM - 1 of one mesh.
@@ -373,8 +375,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     real *lds0 = smem;                               // [NF][BLK] (two sets with DBF)
     real *xch = smem + (DBF ? 2 : 1) * NF * BLK;     // [NX][BLK]
     real *alds = xch + Shape::NX * BLK;   // [EPB][2 DIM + 1]
-    real *llds = alds + Shape::ASL * BLK; // [DIM][BLK]
-    real *clds = llds + DIM * BLK;        // [CS][BLK]
+    real *clds = alds + Shape::ASL * BLK; // [CS][BLK]
     real *xb = clds + Shape::CS * BLK;    // [XB][BLK]
     real *dtab = xb + Shape::XB * BLK;    // DTAB: [DIM][N+1][N+1], dtab[(d n1 + r) n1 + k] = 2 D_{r,(r+k) mod n1}/dx_d
     constexpr bool CSH = Shape::CS > 0;
@@ -459,13 +460,15 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     // Rusanov speed of each face through this node: lambda = max of the
     // wave speeds of u^n on both sides (eq:numflux.cons; MHD: and c_h), from
     // the face data, formed here so that the element can add its own share
-    // of the interface flux itself; kept in LDS until the end of the stages
+    // of the interface flux itself
     constexpr int nfn = DIM == 2 ? n1 : 1;
     using FD = FaceData<EQ, M>;
+    real lamd[DIM];
     {
         const real *ts = (const real *)a.traces;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
+            lamd[d] = real(0);
             if (!onface[d]) continue;
             const int face = 2 * d + side[d], nface = 2 * d + 1 - side[d];
             const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
@@ -476,7 +479,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
             const real sn = wl ? so : ts[((long)(nface * FD::NCT + FD::SPEED) * E + en) * nfn + kk];
             real lam = dmax(so, sn);
             if constexpr (EQ == EQ_MHD) lam = dmax(lam, ctx.ch);
-            llds[d * BLK + tid] = lam;
+            lamd[d] = lam;
         }
     }
 
@@ -557,7 +560,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
     for (int d = 0; d < DIM; ++d) {
         UB[d] = real(0);
         sw[d] = onface[d] ? (side[d] ? -invw[d] : invw[d]) : real(0);
-        hl[d] = onface[d] ? (side[d] ? real(0.5) : real(-0.5)) * llds[d * BLK + tid] : real(0);
+        hl[d] = onface[d] ? (side[d] ? real(0.5) : real(-0.5)) * lamd[d] : real(0);
         oaf[d] = real(1);
         cF[d] = real(0);
         ohl[d] = hl[d];
