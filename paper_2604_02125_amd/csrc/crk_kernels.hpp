@@ -17,15 +17,23 @@ constexpr int MAXN = 4;      // highest compiled degree
 constexpr int MAXS = 6;      // highest stage count
 constexpr int BLOCK = 256;   // lanes per workgroup of the element kernels
 constexpr int RED_BLOCKS = 1024;  // max workgroups of the reduction kernels
+#ifndef CRK_WIDE_TILE
+#define CRK_WIDE_TILE 128
+#endif
 #ifndef CRK_WAVE_TILE
 #define CRK_WAVE_TILE 64
 #endif
 // Workgroup of the local-stage and interface kernels for elements of NP
 // nodes: when whole elements fit a wavefront those kernels need no
 // workgroup barrier, and smaller workgroups finish the grid more evenly.
+// Otherwise (N = 2, 4 in 2D) two wavefronts: a workgroup barrier then waits
+// for one other wavefront only, and the degree-4 MHD kernel, held at one
+// wavefront per SIMD by its registers, fits two workgroups per CU in LDS
+// (Orszag-Tang 192^2: 409 -> 369 us per local phase against 256 lanes;
+// 192 lanes leave one SIMD idle, 64 lanes hold two elements in 50 lanes).
 template <int NP>
-constexpr int tile_block() { return 64 % NP == 0 ? CRK_WAVE_TILE : BLOCK; }
-inline int tile_block_rt(int np) { return 64 % np == 0 ? CRK_WAVE_TILE : BLOCK; }
+constexpr int tile_block() { return 64 % NP == 0 ? CRK_WAVE_TILE : CRK_WIDE_TILE; }
+inline int tile_block_rt(int np) { return 64 % np == 0 ? CRK_WAVE_TILE : CRK_WIDE_TILE; }
 
 // XCD-aware tile order.  Workgroups are dispatched round-robin over the
 // eight XCDs (b -> XCD b mod 8), each with its own L2.  Giving XCD x the
@@ -289,14 +297,15 @@ __device__ __forceinline__ int line_node(const int *pd, int d, int qd)
 }
 
 // Synchronisation of the lanes of one element.  When a wavefront holds
-// whole elements (64 divisible by (N+1)^d: N = 1, 3), every LDS exchange of
-// the local stages stays inside one wavefront, so ordering the wavefront's
-// own LDS accesses suffices and the waves of a workgroup never wait for each
-// other; otherwise the workgroup barrier.
-template <int NP>
+// whole elements (64 divisible by (N+1)^d: N = 1, 3; or single-wavefront
+// workgroups), every LDS exchange of the local stages stays inside one
+// wavefront, so ordering the wavefront's own LDS accesses suffices and the
+// waves of a workgroup never wait for each other; otherwise the workgroup
+// barrier.
+template <int NP, int BLK = BLOCK>
 __device__ __forceinline__ void element_sync()
 {
-    if constexpr (64 % NP == 0) {
+    if constexpr (64 % NP == 0 || BLK <= 64) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -608,10 +617,10 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         real nd[NF];
         Phys::node(us, nd, ctx);
         real *lds = lds0 + ((DBF && (i & 1)) ? NF * BLK : 0);
-        if (i > 0 && !DBF) element_sync<NP>();    // the previous stage has finished reading LDS
+        if (i > 0 && !DBF) element_sync<NP, BLK>();    // the previous stage has finished reading LDS
 #pragma unroll
         for (int f = 0; f < NF; ++f) lds[f * BLK + tid] = nd[f];
-        element_sync<NP>();
+        element_sync<NP, BLK>();
         if (i == 0) {
             if (blend && valid) alpha = alds[le * NA];
             oma = real(1) - alpha;
@@ -643,7 +652,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
             if (i == 0 && blend && alpha > real(0)) {
                 c_own = Phys::sound(nd, ctx);
                 clds[tid] = c_own;
-                element_sync<NP>();
+                element_sync<NP, BLK>();
             }
         }
 #pragma unroll
@@ -771,7 +780,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
             }
         }
         if constexpr (SYM) {
-            element_sync<NP>();
+            element_sync<NP, BLK>();
             if constexpr (BAL) {
                 // the pair of the other direction, from the lane that evaluated it
                 const int src = base + (xm ? line_node<N, DIM>(pd, 1, qy) : line_node<N, DIM>(pd, 0, qx));
@@ -931,7 +940,7 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
     // exchange and sums stay inside the wavefront
     constexpr bool WAVE = (NP & (NP - 1)) == 0 && 64 % NP == 0;
     eps[tid] = eps_node;
-    element_sync<NP>();
+    element_sync<NP, BLK>();
     const int mk = node % n1, ml = DIM == 2 ? node / n1 : 0;
     double rk[n1], rl[n1];
 #pragma unroll

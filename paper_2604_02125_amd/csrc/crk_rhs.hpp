@@ -55,7 +55,7 @@ __device__ __forceinline__ void rhs_lane(const Tables &t, const real *u, const C
     Phys::node(uo, nd, ctx);
 #pragma unroll
     for (int f = 0; f < NF; ++f) lds[f * BLK + tid] = nd[f];
-    element_sync<NP>();
+    element_sync<NP, BLK>();
 
 #pragma unroll
     for (int v = 0; v < M; ++v) R[v] = real(0);
@@ -109,7 +109,7 @@ __device__ __forceinline__ void rhs_lane(const Tables &t, const real *u, const C
         }
     }
     if constexpr (SYM) {
-        element_sync<NP>();
+        element_sync<NP, BLK>();
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
 #pragma unroll
