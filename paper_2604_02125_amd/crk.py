@@ -132,6 +132,12 @@ class Solver:
                  nc_interface=NC_REDUCED, device="cuda"):
         import torch
         self.device = torch.device(device)
+        # the constructor's arguments (checkpoints record them to rebuild the solver)
+        self.config = dict(dim=dim, nx=nx, ny=ny, x0=x0, x1=x1, y0=y0, y1=y1, degree=degree, equation=equation,
+                           gamma=gamma, precision=precision, A=None if A is None else [list(map(float, r)) for r in A],
+                           b=None if b is None else list(map(float, b)), volume_flux=volume_flux, cfl=cfl,
+                           limiter=limiter, alpha_max=alpha_max, alpha_min=alpha_min,
+                           boundary=[int(boundary[0]), int(boundary[1])], nc_interface=int(nc_interface))
         m = MeshDesc(dim, nx, ny, x0, x1, y0, y1, degree, equation, gamma, precision)
         m.boundary[0], m.boundary[1] = int(boundary[0]), int(boundary[1])
         sc = SchemeDesc()

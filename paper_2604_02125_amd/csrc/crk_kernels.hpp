@@ -929,6 +929,21 @@ __device__ __forceinline__ void mark_tiles(const Tables &t, long e, int epb, int
         }
 }
 
+// eps = rho p of a node from its conserved Euler state in FP64, the
+// indicator's input.  One function without contraction for the standalone
+// indicator and the tail of the pipelined interface phase, so that both give
+// the same bits (a pipelined run resumed from its state continues exactly).
+template <int DIM>
+__device__ __forceinline__ double indicator_eps(const double *us, double gamma)
+{
+#pragma clang fp contract(off)
+    double ke = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) ke += us[1 + k] * us[1 + k];
+    const double p = (gamma - 1.0) * (us[DIM + 1] - 0.5 * ke / us[0]);
+    return us[0] * p;
+}
+
 template <int DIM, int N, int BLK>
 __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le, int node, long e, bool valid,
                                                 double eps_node, double *eps, double *en, double *alpha_raw,
@@ -1214,9 +1229,10 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
     }
     if constexpr (EQ == EQ_EULER) {
         if (a.alpha_raw_out != nullptr) {
-            real rho, v[DIM], p, Ev;
-            Phys::prim(nd, rho, v, p, Ev, ctx);
-            indicator_lanes<DIM, N, BLK>(t, tid, le, node, e, valid, (double)rho * (double)p, dsmem + BLK,
+            double ud[M];
+#pragma unroll
+            for (int v = 0; v < M; ++v) ud[v] = (double)u[v];
+            indicator_lanes<DIM, N, BLK>(t, tid, le, node, e, valid, indicator_eps<DIM>(ud, t.gamma), dsmem + BLK,
                                          dsmem + 2 * BLK, a.alpha_raw_out, a.features, a.tiles_out);
         }
     }
@@ -1412,11 +1428,8 @@ __global__ void __launch_bounds__(BLOCK) k_indicator(const Tables t, const void 
     double us[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) us[v] = (double)u[((long)v * E + es) * NP + node];
-    double ke = 0.0;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) ke += us[1 + k] * us[1 + k];
-    const double p = (t.gamma - 1.0) * (us[DIM + 1] - 0.5 * ke / us[0]);
-    indicator_lanes<DIM, N, BLOCK>(t, tid, le, node, e, valid, us[0] * p, eps, en, alpha_raw, features);
+    indicator_lanes<DIM, N, BLOCK>(t, tid, le, node, e, valid, indicator_eps<DIM>(us, t.gamma), eps, en, alpha_raw,
+                                   features);
 }
 
 static __global__ void __launch_bounds__(BLOCK) k_smooth(const Tables t, const double *alpha_raw, double *alpha)
