@@ -383,9 +383,15 @@ struct MhdP {
             return;
         }
         const real h = real(0.5);
-        real rho_ln, ibeta_ln;
-        lnmean_pair(a[0], b[0], a[9], b[9], a[10], b[10], a[11], b[11], rho_ln, ibeta_ln);
-        const real rho_a = h * (a[0] + b[0]), beta_a = h * (a[10] + b[10]), psi_a = h * (a[8] + b[8]);
+        // both logarithmic means and 1/(2 mean beta) from one reciprocal
+        real n1, d1, n2, d2;
+        lnmean_parts_fast(a[0], b[0], a[9], b[9], n1, d1);
+        lnmean_parts_fast(a[10], b[10], a[11], b[11], n2, d2);
+        const real tb = a[10] + b[10];
+        const real dn = d1 * n2;
+        const real r = rcp_nr(dn * tb);
+        const real rho_ln = (n1 * n2) * tb * r, ibeta_ln = (d2 * d1) * tb * r, i2b = dn * r;
+        const real rho_a = h * (a[0] + b[0]), psi_a = h * (a[8] + b[8]);
         real va[3], Ba[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) { va[k] = h * (a[1 + k] + b[1 + k]); Ba[k] = h * (a[5 + k] + b[5 + k]); }
@@ -393,7 +399,7 @@ struct MhdP {
         f[0] = f0;
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            f[1 + k] = f0 * va[k] - Ba[d] * Ba[k] + (k == d ? rho_a * rcp_nr(real(2) * beta_a) + h * h * (a[13] + b[13]) : real(0));
+            f[1 + k] = f0 * va[k] - Ba[d] * Ba[k] + (k == d ? rho_a * i2b + h * h * (a[13] + b[13]) : real(0));
 #pragma unroll
         for (int k = 0; k < 3; ++k) f[5 + k] = (k == d) ? c.ch * psi_a : va[d] * Ba[k] - va[k] * Ba[d];
         f[8] = c.ch * Ba[d];
