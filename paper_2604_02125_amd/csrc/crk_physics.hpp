@@ -298,12 +298,13 @@ struct MhdP {
 
     __device__ __forceinline__ static void node(const real *u, real *nd, const Ctx<real> &c)
     {
-        const real rho = u[0], irho = real(1) / rho;
+        // Newton reciprocals instead of IEEE divisions, as for Euler
+        const real rho = u[0], irho = rcp_nr(rho);
         const real v1 = u[1] * irho, v2 = u[2] * irho, v3 = u[3] * irho;
         const real B1 = u[5], B2 = u[6], B3 = u[7], psi = u[8];
         const real vv = v1 * v1 + v2 * v2 + v3 * v3, BB = B1 * B1 + B2 * B2 + B3 * B3;
         const real p = c.gm1 * (u[4] - real(0.5) * rho * vv - real(0.5) * BB - real(0.5) * psi * psi);
-        const real beta = real(0.5) * rho / p;
+        const real beta = real(0.5) * rho * rcp_nr(p);
         nd[0] = rho; nd[1] = v1; nd[2] = v2; nd[3] = v3; nd[4] = p;
         nd[5] = B1; nd[6] = B2; nd[7] = B3; nd[8] = psi;
         nd[9] = dlog(rho); nd[10] = beta; nd[11] = dlog(beta);
@@ -313,7 +314,7 @@ struct MhdP {
     // the fields that phys(), speed(), fast(), btimes() and cons() read (no logarithms)
     __device__ __forceinline__ static void node_basic(const real *u, real *nd, const Ctx<real> &c)
     {
-        const real rho = u[0], irho = real(1) / rho;
+        const real rho = u[0], irho = rcp_nr(rho);
         const real v1 = u[1] * irho, v2 = u[2] * irho, v3 = u[3] * irho;
         const real B1 = u[5], B2 = u[6], B3 = u[7], psi = u[8];
         const real vv = v1 * v1 + v2 * v2 + v3 * v3, BB = B1 * B1 + B2 * B2 + B3 * B3;
