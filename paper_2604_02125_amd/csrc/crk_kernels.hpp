@@ -1,7 +1,9 @@
 // crk_kernels.hpp -- HIP kernels of one cRKFR step on gfx950.
 //
 // Mapping: one lane per solution node, the (N+1)^d nodes of an element in
-// consecutive lanes, floor(256/(N+1)^d) elements per 256-lane workgroup.
+// consecutive lanes; single-wavefront workgroups where whole elements fit a
+// wavefront, else 128-lane workgroups of floor(128/(N+1)^d) elements (the
+// reductions and the indicator use 256-lane workgroups).
 // A stage stages its per-node fields (primitives, logarithms) in LDS so that
 // every lane can form the two-point fluxes with the nodes on its x- and
 // y-lines; the stage states, stage residuals and time averages stay in
