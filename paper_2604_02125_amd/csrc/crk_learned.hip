@@ -221,14 +221,19 @@ __global__ void __launch_bounds__(256) k_to_bf16(long count, const float *x, uin
 // for the modal indicator.
 // Inference for the blending coefficient on the matrix cores.  One
 // wavefront takes tiles of 16 elements and forms each layer transposed,
-// Y^T = W X^T, with v_mfma_f32_16x16x16_bf16: the BF16 weights are the exact
-// A operand, and every FP32 activation enters the B operand as the sum of
-// three BF16 parts (x = hi + mid + lo to within 2^-24 |x|), so each product
-// is exact in FP32 and the result is the FP32 network up to the summation
-// order.  16x16x16 operand layout (lane l, i = 0..3): A[l % 16][4 (l / 16) + i],
-// B[4 (l / 16) + i][l % 16], D[4 (l / 16) + i][l % 16]; a layer's D is
-// therefore already the B operand of the next layer.  The weights stay in
-// registers while the wavefront walks its tiles.
+// Y^T = W X^T: the BF16 weights are the exact A operand, and every FP32
+// activation enters the B operand as the sum of three BF16 parts
+// (x = hi + mid + lo to within 2^-24 |x|), so each product is exact in FP32
+// and the result is the FP32 network up to the summation order.  The first
+// layer (16 inputs) uses v_mfma_f32_16x16x16_bf16, operand layout (lane l,
+// i = 0..3): A[l % 16][4 (l / 16) + i], B[4 (l / 16) + i][l % 16],
+// D[4 (l / 16) + i][l % 16]; a layer's D is therefore already a B operand of
+// the next layer.  The second layer (64 hidden inputs) uses the K = 32 form
+// v_mfma_f32_16x16x32_bf16 on two 16-row D blocks at a time: a lane's eight
+// B values are its four rows of each block, and its eight A values are the
+// weights of the same hidden units (whatever hidden unit an operand slot
+// carries, A and B carry the same one, so the sum runs over the block pair).
+// The weights stay in registers while the wavefront walks its tiles.
 typedef short mx_s4 __attribute__((ext_vector_type(4)));
 typedef float mx_f4 __attribute__((ext_vector_type(4)));
 
@@ -252,6 +257,26 @@ __device__ __forceinline__ mx_f4 mfma3(const mx_s4 &a, const mx_s4 &bh, const mx
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bl, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bm, acc, 0, 0, 0);
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bh, acc, 0, 0, 0);
+}
+
+typedef __bf16 mx_b8 __attribute__((ext_vector_type(8)));
+typedef short mx_s8 __attribute__((ext_vector_type(8)));
+
+// two 4-value operands of the K = 16 form as one 8-value operand of the
+// K = 32 form, reinterpreted as a whole vector (built element by element
+// from bit-cast BF16 values, the operand reached the instruction wrongly
+// packed with this compiler, although its bits read back unchanged)
+__device__ __forceinline__ mx_b8 join8(const mx_s4 &p, const mx_s4 &q)
+{
+    const mx_s8 t = __builtin_shufflevector(p, q, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(mx_b8, t);
+}
+
+__device__ __forceinline__ mx_f4 mfma3k32(const mx_b8 &a, const mx_b8 &bh, const mx_b8 &bm, const mx_b8 &bl, mx_f4 acc)
+{
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bm, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc, 0, 0, 0);
 }
 
 constexpr int MX_TILE = 16;
@@ -287,6 +312,11 @@ __global__ void __launch_bounds__(256) k_mlp_alpha(const uint16_t *theta, const 
 #pragma unroll
             for (int i = 0; i < 4; ++i) A2[c][b][i] = (short)w.W2[(16 * c + col) * HID + 16 * b + 4 * kq + i];
     }
+    mx_b8 A2k[4][2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) A2k[c][kb] = join8(A2[c][2 * kb], A2[c][2 * kb + 1]);
     const float b3 = bf2f(w.b3[0]);
     float flo[4], fhi[4];
 #pragma unroll
@@ -321,13 +351,21 @@ __global__ void __launch_bounds__(256) k_mlp_alpha(const uint16_t *theta, const 
         mx_s4 hh[4], hm[4], hl[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) split3(h1[b], hh[b], hm[b], hl[b]);
-        // layer 2 and the output layer's partial dot product
+        // layer 2 (K = 32: hidden blocks 2 kb and 2 kb + 1 together) and the
+        // output layer's partial dot product
+        mx_b8 kh[2], km[2], kl[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            kh[kb] = join8(hh[2 * kb], hh[2 * kb + 1]);
+            km[kb] = join8(hm[2 * kb], hm[2 * kb + 1]);
+            kl[kb] = join8(hl[2 * kb], hl[2 * kb + 1]);
+        }
         float z = 0.f;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             mx_f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc = mfma3(A2[c][b], hh[b], hm[b], hl[b], acc);
+            for (int kb = 0; kb < 2; ++kb) acc = mfma3k32(A2k[c][kb], kh[kb], km[kb], kl[kb], acc);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float v = acc[i] + B2[c][i];
