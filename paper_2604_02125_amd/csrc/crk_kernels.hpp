@@ -946,6 +946,17 @@ __device__ __forceinline__ double indicator_eps(const double *us, double gamma)
     return us[0] * p;
 }
 
+// a double moved across lanes by a DPP control (CTRL a compile-time control
+// word; every source lane exists for the quad permutations and the row
+// rotations used here)
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double x)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 template <int DIM, int N, int BLK>
 __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le, int node, long e, bool valid,
                                                 double eps_node, double *eps, double *en, double *alpha_raw,
@@ -956,16 +967,34 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
     // an element's lanes are one aligned power-of-two group of a wavefront:
     // exchange and sums stay inside the wavefront
     constexpr bool WAVE = (NP & (NP - 1)) == 0 && 64 % NP == 0;
+    // degree 3 in 2D: an element is one 16-lane DPP row and each of its node
+    // rows (4 lanes) one quad, so the separable transform m = V (V eps)^T
+    // moves its values with quad permutations and row rotations, without LDS
+    constexpr bool DPP = DIM == 2 && N == 3 && WAVE;
+    const int mk = node % n1, ml = DIM == 2 ? node / n1 : 0;
+    double m = 0.0;
+    if constexpr (DPP) {
+        // a(mk, j) = sum_i V[mk][i] eps(i, j): eps of the lane's node row by
+        // quad broadcasts (lane 4 j + i holds eps(i, j))
+        double a = t.Vinv[mk][0] * dpp_double<0x00>(eps_node);
+        a += t.Vinv[mk][1] * dpp_double<0x55>(eps_node);
+        a += t.Vinv[mk][2] * dpp_double<0xAA>(eps_node);
+        a += t.Vinv[mk][3] * dpp_double<0xFF>(eps_node);
+        // m(mk, ml) = sum_j V[ml][j] a(mk, j): rotating the row right by
+        // 4 s brings a(mk, (ml - s) mod 4) from lane 4 ((ml - s) mod 4) + mk
+        m = t.Vinv[ml][ml] * a;
+        m += t.Vinv[ml][(ml + 3) & 3] * dpp_double<0x124>(a);
+        m += t.Vinv[ml][(ml + 2) & 3] * dpp_double<0x128>(a);
+        m += t.Vinv[ml][(ml + 1) & 3] * dpp_double<0x12C>(a);
+    } else {
     eps[tid] = eps_node;
     element_sync<NP, BLK>();
-    const int mk = node % n1, ml = DIM == 2 ? node / n1 : 0;
     double rk[n1], rl[n1];
 #pragma unroll
     for (int c = 0; c < n1; ++c) {
         rk[c] = t.Vinv[mk][c];
         rl[c] = t.Vinv[ml][c];
     }
-    double m = 0.0;
     if constexpr (DIM == 1) {
 #pragma unroll
         for (int i = 0; i < n1; ++i) m += rk[i] * eps[le * NP + i];
@@ -977,6 +1006,7 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
             for (int i = 0; i < n1; ++i) sj += rk[i] * eps[le * NP + j * n1 + i];
             m += rl[j] * sj;
         }
+    }
     }
     const double e2 = m * m;
     const double x1 = (mk <= N - 1 && ml <= N - 1) ? e2 : 0.0;
@@ -1002,7 +1032,10 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
     }
     if (valid) {
         // every lane of the element forms the same coefficient
-        const double E1 = (tot - c1) / tot, E2 = (c1 - c2) / c1;
+        // both energy fractions from one Newton reciprocal (tot, c1 > 0: they
+        // hold the mean's energy)
+        const double r = rcp_nr(tot * c1);
+        const double E1 = (tot - c1) * (c1 * r), E2 = (c1 - c2) * (tot * r);
         const double En = E1 > E2 ? E1 : E2;
         double al = 1.0 / (1.0 + exp(-(t.ind_sharpness / t.ind_threshold) * (En - t.ind_threshold)));
         if (al < t.alpha_min) al = 0.0;
