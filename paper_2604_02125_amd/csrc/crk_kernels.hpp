@@ -427,11 +427,16 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         invw[d] = real(t.invw_dx[d][r]);
     }
     if constexpr (DTAB) {
-        // visible to every lane after the first stage's barrier
-        if (tid < DIM * n1 * n1) {
-            const int d = tid / (n1 * n1), r = (tid / n1) % n1, k = tid % n1;
+        // every wavefront writes the whole table (the same values), so that
+        // it is visible to the wavefront's own lanes after the first stage's
+        // synchronisation also where that is wavefront-scope and the tile
+        // spans several wavefronts (the batched tiles)
+        static_assert(DIM * (N + 1) * (N + 1) <= 64, "one wavefront writes the table");
+        const int wl = tid & 63;
+        if (wl < DIM * n1 * n1) {
+            const int d = wl / (n1 * n1), r = (wl / n1) % n1, k = wl % n1;
             const int q = r + k < n1 ? r + k : r + k - n1;
-            dtab[tid] = real(2.0 * t.D[r][q] * t.invdx[d]);
+            dtab[wl] = real(2.0 * t.D[r][q] * t.invdx[d]);
         }
     }
     // 2 D_{p,q}/dx_d of rotation k = 1..N (k = 0: the diagonal)
@@ -987,26 +992,26 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
         m += t.Vinv[ml][(ml + 2) & 3] * dpp_double<0x128>(a);
         m += t.Vinv[ml][(ml + 1) & 3] * dpp_double<0x12C>(a);
     } else {
-    eps[tid] = eps_node;
-    element_sync<NP, BLK>();
-    double rk[n1], rl[n1];
+        eps[tid] = eps_node;
+        element_sync<NP, BLK>();
+        double rk[n1], rl[n1];
 #pragma unroll
-    for (int c = 0; c < n1; ++c) {
-        rk[c] = t.Vinv[mk][c];
-        rl[c] = t.Vinv[ml][c];
-    }
-    if constexpr (DIM == 1) {
-#pragma unroll
-        for (int i = 0; i < n1; ++i) m += rk[i] * eps[le * NP + i];
-    } else {
-#pragma unroll
-        for (int j = 0; j < n1; ++j) {
-            double sj = 0.0;
-#pragma unroll
-            for (int i = 0; i < n1; ++i) sj += rk[i] * eps[le * NP + j * n1 + i];
-            m += rl[j] * sj;
+        for (int c = 0; c < n1; ++c) {
+            rk[c] = t.Vinv[mk][c];
+            rl[c] = t.Vinv[ml][c];
         }
-    }
+        if constexpr (DIM == 1) {
+#pragma unroll
+            for (int i = 0; i < n1; ++i) m += rk[i] * eps[le * NP + i];
+        } else {
+#pragma unroll
+            for (int j = 0; j < n1; ++j) {
+                double sj = 0.0;
+#pragma unroll
+                for (int i = 0; i < n1; ++i) sj += rk[i] * eps[le * NP + j * n1 + i];
+                m += rl[j] * sj;
+            }
+        }
     }
     const double e2 = m * m;
     const double x1 = (mk <= N - 1 && ml <= N - 1) ? e2 : 0.0;
