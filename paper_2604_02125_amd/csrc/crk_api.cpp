@@ -299,6 +299,24 @@ crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables
         return fail(CRK_ERR_UNSUPPORTED,
                     "the stage-wise interface flux is compiled for classical RK4 and Butcher's six-stage method");
     modal_inverse(t.N, xi, w, t.Vinv);
+    for (int d = 0; d < 2; ++d)
+        for (int r = 0; r <= t.N; ++r) {
+            for (int k = 0; k <= t.N; ++k) {
+                const int q = r + k <= t.N ? r + k : r + k - (t.N + 1);
+                t.dk[d][r][k] = 2.0 * t.D[r][q] * t.invdx[d];
+                t.dkf[d][r][k] = (float)t.dk[d][r][k];
+            }
+            t.invw_dxf[d][r] = (float)t.invw_dx[d][r];
+        }
+    for (int i = 0; i < MAXS; ++i) {
+        t.bf[i] = (float)t.b[i];
+        for (int j = 0; j < MAXS; ++j) t.Af[i][j] = (float)t.A[i][j];
+    }
+    t.gm1 = t.gamma - 1.0;
+    t.inv_gm1 = 1.0 / (t.gamma - 1.0);
+    t.gammaf = (float)t.gamma;
+    t.gm1f = (float)t.gm1;
+    t.inv_gm1f = (float)t.inv_gm1;
     t.ind_threshold = 0.5 * std::pow(10.0, -1.8 * std::pow(t.N + 1.0, 0.25));
     t.ind_sharpness = std::log((1.0 - 1e-4) / 1e-4);
     t.alpha_min = sc->alpha_min;

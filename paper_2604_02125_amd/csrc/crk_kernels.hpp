@@ -91,6 +91,30 @@ struct Tables {
     double Vinv[MAXN + 1][MAXN + 1];  // nodal -> orthonormal Legendre modal
     double cfl;
     double ind_threshold, ind_sharpness, alpha_min, alpha_max;
+    // formed once on the host for the local stages (the float copies for the
+    // FP32 kernels, each the rounded double): dk[d][r][k] = 2 D_{r,(r+k) mod
+    // (N+1)} / dx_d (k = 0: the diagonal), gamma - 1 and 1/(gamma - 1)
+    double dk[2][MAXN + 1][MAXN + 1];
+    float dkf[2][MAXN + 1][MAXN + 1];
+    float invw_dxf[2][MAXN + 1];
+    float Af[MAXS][MAXS], bf[MAXS];
+    double gm1, inv_gm1;
+    float gammaf, gm1f, inv_gm1f;
+};
+
+// The host-formed coefficients in the kernel's precision.
+template <typename real> struct Tab;
+template <> struct Tab<double> {
+    static __device__ __forceinline__ double dk(const Tables &t, int d, int r, int k) { return t.dk[d][r][k]; }
+    static __device__ __forceinline__ double invw(const Tables &t, int d, int r) { return t.invw_dx[d][r]; }
+    static __device__ __forceinline__ double A(const Tables &t, int i, int j) { return t.A[i][j]; }
+    static __device__ __forceinline__ double b(const Tables &t, int i) { return t.b[i]; }
+};
+template <> struct Tab<float> {
+    static __device__ __forceinline__ float dk(const Tables &t, int d, int r, int k) { return t.dkf[d][r][k]; }
+    static __device__ __forceinline__ float invw(const Tables &t, int d, int r) { return t.invw_dxf[d][r]; }
+    static __device__ __forceinline__ float A(const Tables &t, int i, int j) { return t.Af[i][j]; }
+    static __device__ __forceinline__ float b(const Tables &t, int i) { return t.bf[i]; }
 };
 
 // Which entries a_ki (k > i) of the stage matrix a kernel may treat as
@@ -210,9 +234,15 @@ template <typename real>
 __device__ __forceinline__ Ctx<real> make_ctx(const Tables &t, const double *dt)
 {
     Ctx<real> c;
-    c.gamma = real(t.gamma);
-    c.gm1 = real(t.gamma - 1.0);
-    c.inv_gm1 = real(1.0 / (t.gamma - 1.0));
+    if constexpr (sizeof(real) == 8) {
+        c.gamma = real(t.gamma);
+        c.gm1 = real(t.gm1);
+        c.inv_gm1 = real(t.inv_gm1);
+    } else {
+        c.gamma = real(t.gammaf);
+        c.gm1 = real(t.gm1f);
+        c.inv_gm1 = real(t.inv_gm1f);
+    }
     c.ch = dt ? real(dt[1]) : real(0);
     return c;
 }
@@ -418,13 +448,10 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         const int r = pd[d];
         if constexpr (!DTAB) {
 #pragma unroll
-            for (int k = 1; k <= N; ++k) {
-                const int q = r + k < n1 ? r + k : r + k - n1;
-                Dk[d][k - 1] = real(2.0 * t.D[r][q] * t.invdx[d]);
-            }
-            Ddiag[d] = real(2.0 * t.D[r][r] * t.invdx[d]);
+            for (int k = 1; k <= N; ++k) Dk[d][k - 1] = Tab<real>::dk(t, d, r, k);
+            Ddiag[d] = Tab<real>::dk(t, d, r, 0);
         }
-        invw[d] = real(t.invw_dx[d][r]);
+        invw[d] = Tab<real>::invw(t, d, r);
     }
     if constexpr (DTAB) {
         // every wavefront writes the whole table (the same values), so that
@@ -435,8 +462,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         const int wl = tid & 63;
         if (wl < DIM * n1 * n1) {
             const int d = wl / (n1 * n1), r = (wl / n1) % n1, k = wl % n1;
-            const int q = r + k < n1 ? r + k : r + k - n1;
-            dtab[wl] = real(2.0 * t.D[r][q] * t.invdx[d]);
+            dtab[wl] = Tab<real>::dk(t, d, r, k);
         }
     }
     // 2 D_{p,q}/dx_d of rotation k = 1..N (k = 0: the diagonal)
@@ -586,10 +612,10 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         real us[M];
-        const real cz = (TAB == 1 && i > 0) ? rdt * real(t.A[i][i > 0 ? i - 1 : 0]) : rdt;
+        const real cz = (TAB == 1 && i > 0) ? rdt * Tab<real>::A(t, i, i > 0 ? i - 1 : 0) : rdt;
 #pragma unroll
         for (int v = 0; v < M; ++v) us[v] = (i == 0) ? un[v] : un[v] - cz * Z[i][v];
-        const real bi = real(t.b[i]);
+        const real bi = Tab<real>::b(t, i);
         if (i > 0) {
             // the u^(i) terms of P_d and W (those of u^(0) = u^n follow the
             // first barrier, where the blending factors are known)
@@ -819,7 +845,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 #pragma unroll
             for (int k = i + 1; k < S; ++k) {
                 if (!stage_coupled<TAB>(k, i)) continue;
-                const real aki = real(t.A[k][i]);
+                const real aki = Tab<real>::A(t, k, i);
 #pragma unroll
                 for (int v = 0; v < M; ++v) Z[k][v] += aki * R[v];
             }
