@@ -319,6 +319,15 @@ crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables
     t.inv_gm1f = (float)t.inv_gm1;
     t.ind_threshold = 0.5 * std::pow(10.0, -1.8 * std::pow(t.N + 1.0, 0.25));
     t.ind_sharpness = std::log((1.0 - 1e-4) / 1e-4);
+    t.ind_slope = t.ind_sharpness / t.ind_threshold;
+    // the logistic value 1/(1 + exp(-slope (E - threshold))) equals alpha_min
+    // at E* = threshold - ln(1/alpha_min - 1)/slope; 0.1 % of the threshold
+    // below E* it is smaller by a factor (1 - 0.009) or so, far beyond the
+    // few-ulp error of evaluating it, so the comparison with alpha_min cannot
+    // go the other way
+    t.ind_en_zero = (sc->alpha_min > 0.0 && sc->alpha_min < 0.5)
+                        ? t.ind_threshold - std::log(1.0 / sc->alpha_min - 1.0) / t.ind_slope - 1e-3 * t.ind_threshold
+                        : -INFINITY;
     t.alpha_min = sc->alpha_min;
     t.alpha_max = sc->alpha_max;
     return CRK_OK;

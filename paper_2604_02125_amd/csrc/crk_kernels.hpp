@@ -100,6 +100,10 @@ struct Tables {
     float Af[MAXS][MAXS], bf[MAXS];
     double gm1, inv_gm1;
     float gammaf, gm1f, inv_gm1f;
+    // modal indicator: sharpness / threshold, and an energy below which the
+    // logistic value is under alpha_min by a wide margin (so the coefficient
+    // is zero without evaluating it)
+    double ind_slope, ind_en_zero;
 };
 
 // The host-formed coefficients in the kernel's precision.
@@ -1068,8 +1072,11 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
         const double r = rcp_nr(tot * c1);
         const double E1 = (tot - c1) * (c1 * r), E2 = (c1 - c2) * (tot * r);
         const double En = E1 > E2 ? E1 : E2;
-        double al = 1.0 / (1.0 + exp(-(t.ind_sharpness / t.ind_threshold) * (En - t.ind_threshold)));
-        if (al < t.alpha_min) al = 0.0;
+        double al = 0.0;
+        if (!(En < t.ind_en_zero)) {   // (a non-finite energy takes the full evaluation)
+            al = 1.0 / (1.0 + exp(-t.ind_slope * (En - t.ind_threshold)));
+            if (al < t.alpha_min) al = 0.0;
+        }
         if (al > 1.0 - t.alpha_min) al = 1.0;
         if (al > t.alpha_max) al = t.alpha_max;
         if (node == 0) alpha_raw[e] = al;
