@@ -243,7 +243,12 @@ crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables
     t.wall[0] = m->boundary[0] == CRK_BC_WALL ? 1 : 0;
     t.wall[1] = (m->dim == 2 && m->boundary[1] == CRK_BC_WALL) ? 1 : 0;
     t.invdx[0] = m->nx / (m->x1 - m->x0);
-    t.inv_nx = 1.0 / m->nx;
+    {
+        int l = 0;
+        while ((1L << l) < m->nx) ++l;
+        t.nx_s = 31 + l;
+        t.nx_m = (1ULL << t.nx_s) / (unsigned long long)m->nx + 1;
+    }
     t.invdx[1] = m->dim == 2 ? m->ny / (m->y1 - m->y0) : 0.0;
     t.gamma = m->gamma;
     t.cfl = sc->cfl;

@@ -79,7 +79,6 @@ struct Tables {
     int dim, nx, ny, N, M, nelem, nnode, nface;  // nface = nodes per face
     int wall[2];                      // per direction: reflective walls instead of periodic wrap
     double invdx[2];
-    double inv_nx;                    // 1/nx, for the element coordinates
     double gamma;
     int stages;
     int tableau;                      // sparsity class of A: see stage_coupled()
@@ -104,6 +103,11 @@ struct Tables {
     // logistic value is under alpha_min by a wide margin (so the coefficient
     // is zero without evaluating it)
     double ind_slope, ind_en_zero;
+    // row of an element without a division: ey = floor(e / nx) = (e nx_m) >> nx_s
+    // for every 0 <= e < 2^31 (nx_s = 31 + ceil(log2 nx), nx_m = floor(2^nx_s / nx) + 1;
+    // Granlund and Montgomery's multiply-and-shift division)
+    unsigned long long nx_m;
+    int nx_s;
 };
 
 // The host-formed coefficients in the kernel's precision.
@@ -211,11 +215,9 @@ __device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
         r.wall = (w0 ? 1 : 0) | (w1 ? 2 : 0);
         return r;
     }
-    int ey = (int)floor((double)ei * t.inv_nx);
-    int ex = ei - ey * nx;
-    if (ex < 0) { --ey; ex += nx; }
-    else if (ex >= nx) { ++ey; ex -= nx; }
+    const int ey = (int)(((unsigned long long)(unsigned)ei * t.nx_m) >> t.nx_s);
     const int row = ey * nx;
+    const int ex = ei - row;
     const bool wx0 = t.wall[0] && ex == 0, wx1 = t.wall[0] && ex + 1 == nx;
     const bool wy0 = t.wall[1] && ey == 0, wy1 = t.wall[1] && ey + 1 == t.ny;
     r.n[0][0] = wx0 ? ei : row + (ex == 0 ? nx - 1 : ex - 1);
@@ -1088,7 +1090,7 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
         if constexpr (DIM == 2) {
             if (tiles != nullptr && al > 0.0) {
                 const int nx = t.nx, ny = t.ny, ei = (int)e;
-                const int ey = ei / nx, ex = ei - ey * nx;
+                const int ey = (int)(((unsigned long long)(unsigned)ei * t.nx_m) >> t.nx_s), ex = ei - ey * nx;
 #pragma unroll
                 for (int j0 = 0; j0 < 13; j0 += NP) {
                     const int j = j0 + node;
@@ -1103,7 +1105,12 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
                         dx = (r & 1) ? 1 : -1;
                         dy = (r & 2) ? 1 : -1;
                     }
-                    const int x = ((ex + dx) % nx + nx) % nx, y = ((ey + dy) % ny + ny) % ny;
+                    // periodic wrap of offsets |dx|, |dy| <= 2 (loops for meshes narrower than that)
+                    int x = ex + dx, y = ey + dy;
+                    while (x < 0) x += nx;
+                    while (x >= nx) x -= nx;
+                    while (y < 0) y += ny;
+                    while (y >= ny) y -= ny;
                     tiles[(y * nx + x) / (BLK / NP)] = 1;
                 }
             }
