@@ -11,6 +11,7 @@
 // index fastest, so a wavefront touches contiguous memory.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include "crk_physics.hpp"
 
 namespace crk {
@@ -202,13 +203,14 @@ struct Nbrs {
     long n[2][2];   // [d][side]
     int wall;       // bit 2d + side: that face lies on a wall
 };
-template <int DIM>
+// (WALLS = false: the caller has checked that the mesh has no walls)
+template <int DIM, bool WALLS = true>
 __device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
 {
     Nbrs r;
     const int nx = t.nx, ei = (int)e;
     if constexpr (DIM == 1) {
-        const bool w0 = t.wall[0] && ei == 0, w1 = t.wall[0] && ei + 1 == nx;
+        const bool w0 = WALLS && t.wall[0] && ei == 0, w1 = WALLS && t.wall[0] && ei + 1 == nx;
         r.n[0][0] = w0 ? ei : (ei == 0 ? nx - 1 : ei - 1);
         r.n[0][1] = w1 ? ei : (ei + 1 == nx ? 0 : ei + 1);
         r.n[1][0] = r.n[1][1] = e;
@@ -218,8 +220,8 @@ __device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
     const int ey = (int)(((unsigned long long)(unsigned)ei * t.nx_m) >> t.nx_s);
     const int row = ey * nx;
     const int ex = ei - row;
-    const bool wx0 = t.wall[0] && ex == 0, wx1 = t.wall[0] && ex + 1 == nx;
-    const bool wy0 = t.wall[1] && ey == 0, wy1 = t.wall[1] && ey + 1 == t.ny;
+    const bool wx0 = WALLS && t.wall[0] && ex == 0, wx1 = WALLS && t.wall[0] && ex + 1 == nx;
+    const bool wy0 = WALLS && t.wall[1] && ey == 0, wy1 = WALLS && t.wall[1] && ey + 1 == t.ny;
     r.n[0][0] = wx0 ? ei : row + (ex == 0 ? nx - 1 : ex - 1);
     r.n[0][1] = wx1 ? ei : row + (ex + 1 == nx ? 0 : ex + 1);
     r.n[1][0] = wy0 ? ei : (ey == 0 ? (t.ny - 1) * nx : row - nx) + ex;
@@ -503,16 +505,18 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         onface[d] = (pd[d] == 0) || (pd[d] == N);
         side[d] = (pd[d] == N) ? 1 : 0;
     }
-    const Nbrs nb = neighbours<DIM>(t, es);
-
     // Rusanov speed of each face through this node: lambda = max of the
     // wave speeds of u^n on both sides (eq:numflux.cons; MHD: and c_h), from
     // the face data, formed here so that the element can add its own share
-    // of the interface flux itself
+    // of the interface flux itself.  Meshes without walls (a uniform test)
+    // take a copy of this part compiled without the wall cases.
     constexpr int nfn = DIM == 2 ? n1 : 1;
     using FD = FaceData<EQ, M>;
     real lamd[DIM];
-    {
+    Nbrs nb;
+    auto face_speeds = [&](auto walls) {
+        constexpr bool W = decltype(walls)::value;
+        nb = neighbours<DIM, W>(t, es);
         const real *ts = (const real *)a.traces;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
@@ -523,13 +527,15 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
             const long en = side[d] ? nb.n[d][1] : nb.n[d][0];
             const real so = ts[((long)(face * FD::NCT + FD::SPEED) * E + es) * nfn + kk];
             // beyond a wall, the mirror image has the element's own wave speed
-            const bool wl = (nb.wall >> face) & 1;
+            const bool wl = W && ((nb.wall >> face) & 1);
             const real sn = wl ? so : ts[((long)(nface * FD::NCT + FD::SPEED) * E + en) * nfn + kk];
             real lam = dmax(so, sn);
             if constexpr (EQ == EQ_MHD) lam = dmax(lam, ctx.ch);
             lamd[d] = lam;
         }
-    }
+    };
+    if (t.wall[0] | t.wall[1]) face_speeds(std::true_type{});
+    else face_speeds(std::false_type{});
 
     // blending coefficients of the element (slot 0) and of its face
     // neighbours (slot 1 + 2d + side), formed by the first lanes of the
@@ -1213,11 +1219,13 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
 #pragma unroll
         for (int v = 0; v < M; ++v) u[v] = real(v == 0 ? 1 : 0);
     }
-    if (face_lane) {
+    // (meshes without walls, a uniform test, take a copy compiled without the wall cases)
+    auto face_update = [&](auto walls) {
+        constexpr bool W = decltype(walls)::value;
         // the neighbour's share of the interface flux (the own share and the
         // own trace term were applied by the local phase), lifted with
         // dg_R/dxi = delta_pN/w_N, dg_L/dxi = -delta_p0/w_0
-        const Nbrs nb = neighbours<DIM>(t, e);
+        const Nbrs nb = neighbours<DIM, W>(t, e);
         real ndo[NF];
         if constexpr (EQ == EQ_MHD) {
             const real *uin = (const real *)a.u_in;
@@ -1237,7 +1245,7 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
             // negates the normal momentum), whose share is -R P of the
             // element's own P: f_d(R u) = -R f_d(u) for every state, so both
             // the time averages and the first-order part mirror that way.
-            const bool wl = (nb.wall >> (2 * d + side)) & 1;
+            const bool wl = W && ((nb.wall >> (2 * d + side)) & 1);
             const real *tn = wl ? tr + ((long)(2 * d + side) * FD::NCT * E + e) * nf + kk
                                 : tr + ((long)nface * FD::NCT * E + en) * nf + kk;
             real jump[M];
@@ -1279,6 +1287,10 @@ __device__ __forceinline__ void interface_tile(const Tables &t, const StepPtrs &
 #pragma unroll
             for (int v = 0; v < M; ++v) u[v] += side ? -coef * jump[v] : coef * jump[v];
         }
+    };
+    if (face_lane) {
+        if (t.wall[0] | t.wall[1]) face_update(std::true_type{});
+        else face_update(std::false_type{});
     }
     // the pipelined step has every node in registers and writes whole
     // elements (whole cache lines: no read of the lines it only partly
