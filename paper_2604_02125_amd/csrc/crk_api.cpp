@@ -247,7 +247,7 @@ crk_status fill_tables(const crk_mesh_desc *m, const crk_scheme_desc *sc, Tables
         int l = 0;
         while ((1L << l) < m->nx) ++l;
         t.nx_s = 31 + l;
-        t.nx_m = (1ULL << t.nx_s) / (unsigned long long)m->nx + 1;
+        t.nx_m = (unsigned)((1ULL << t.nx_s) / (unsigned long long)m->nx + 1);
     }
     t.invdx[1] = m->dim == 2 ? m->ny / (m->y1 - m->y0) : 0.0;
     t.gamma = m->gamma;

@@ -107,7 +107,7 @@ struct Tables {
     // row of an element without a division: ey = floor(e / nx) = (e nx_m) >> nx_s
     // for every 0 <= e < 2^31 (nx_s = 31 + ceil(log2 nx), nx_m = floor(2^nx_s / nx) + 1;
     // Granlund and Montgomery's multiply-and-shift division)
-    unsigned long long nx_m;
+    unsigned nx_m;   // < 2^32 for dividends below 2^31
     int nx_s;
 };
 
@@ -217,7 +217,7 @@ __device__ __forceinline__ Nbrs neighbours(const Tables &t, long e)
         r.wall = (w0 ? 1 : 0) | (w1 ? 2 : 0);
         return r;
     }
-    const int ey = (int)(((unsigned long long)(unsigned)ei * t.nx_m) >> t.nx_s);
+    const int ey = (int)(((unsigned long long)(unsigned)ei * (unsigned long long)t.nx_m) >> t.nx_s);
     const int row = ey * nx;
     const int ex = ei - row;
     const bool wx0 = WALLS && t.wall[0] && ex == 0, wx1 = WALLS && t.wall[0] && ex + 1 == nx;
@@ -1096,7 +1096,7 @@ __device__ __forceinline__ void indicator_lanes(const Tables &t, int tid, int le
         if constexpr (DIM == 2) {
             if (tiles != nullptr && al > 0.0) {
                 const int nx = t.nx, ny = t.ny, ei = (int)e;
-                const int ey = (int)(((unsigned long long)(unsigned)ei * t.nx_m) >> t.nx_s), ex = ei - ey * nx;
+                const int ey = (int)(((unsigned long long)(unsigned)ei * (unsigned long long)t.nx_m) >> t.nx_s), ex = ei - ey * nx;
 #pragma unroll
                 for (int j0 = 0; j0 < 13; j0 += NP) {
                     const int j = j0 + node;
