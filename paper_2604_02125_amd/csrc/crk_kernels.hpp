@@ -569,7 +569,9 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                     for (int sd = 0; sd < 2; ++sd) am = fmax(am, 0.5 * a.alpha_raw[nb.n[d][sd]]);
                 a.alpha_s[e] = am;
             } else {
-                const Nbrs nt = neighbours<DIM>(t, tg);
+                Nbrs nt;
+                if (t.wall[0] | t.wall[1]) nt = neighbours<DIM, true>(t, tg);
+                else nt = neighbours<DIM, false>(t, tg);
                 am = a.alpha_raw[tg];
 #pragma unroll
                 for (int d = 0; d < DIM; ++d)
