@@ -115,12 +115,21 @@ struct Tables {
 template <typename real> struct Tab;
 template <> struct Tab<double> {
     static __device__ __forceinline__ double dk(const Tables &t, int d, int r, int k) { return t.dk[d][r][k]; }
+    // D_{r,q} / dx_d: half of dk at rotation (q - r) mod (N+1), exactly (a power of two)
+    static __device__ __forceinline__ double dn(const Tables &t, int d, int r, int q)
+    {
+        return 0.5 * t.dk[d][r][q - r < 0 ? q - r + t.N + 1 : q - r];
+    }
     static __device__ __forceinline__ double invw(const Tables &t, int d, int r) { return t.invw_dx[d][r]; }
     static __device__ __forceinline__ double A(const Tables &t, int i, int j) { return t.A[i][j]; }
     static __device__ __forceinline__ double b(const Tables &t, int i) { return t.b[i]; }
 };
 template <> struct Tab<float> {
     static __device__ __forceinline__ float dk(const Tables &t, int d, int r, int k) { return t.dkf[d][r][k]; }
+    static __device__ __forceinline__ float dn(const Tables &t, int d, int r, int q)
+    {
+        return 0.5f * t.dkf[d][r][q - r < 0 ? q - r + t.N + 1 : q - r];
+    }
     static __device__ __forceinline__ float invw(const Tables &t, int d, int r) { return t.invw_dxf[d][r]; }
     static __device__ __forceinline__ float A(const Tables &t, int i, int j) { return t.Af[i][j]; }
     static __device__ __forceinline__ float b(const Tables &t, int i) { return t.bf[i]; }
@@ -484,13 +493,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
 #pragma unroll
-            for (int q = 0; q < n1; ++q) {
-                real c = real(0);
-#pragma unroll
-                for (int r = 0; r < n1; ++r)
-                    if (pd[d] == r) c = real(t.D[r][q] * t.invdx[d]);
-                Dn[d][q] = c;
-            }
+            for (int q = 0; q < n1; ++q) Dn[d][q] = Tab<real>::dn(t, d, pd[d], q);
     }
 
     const real *uin = (const real *)a.u_in;

@@ -74,7 +74,7 @@ __device__ __forceinline__ void rhs_lane(const Tables &t, const real *u, const C
 #pragma unroll
             for (int f = 0; f < NF; ++f) ndq[f] = lds[f * BLK + base + q];
             Phys::pair(d, nd, ndq, fs, ctx);
-            const real c = real(2.0 * t.D[r][qd] * t.invdx[d]);
+            const real c = Tab<real>::dk(t, d, r, k);
 #pragma unroll
             for (int v = 0; v < M; ++v) R[v] += c * fs[v];
             if constexpr (SYM) {
@@ -89,7 +89,7 @@ __device__ __forceinline__ void rhs_lane(const Tables &t, const real *u, const C
             real fp[M];
             if constexpr (EQ == EQ_EULER) Phys::phys_cons(d, uo, nd, fp, ctx);
             else Phys::phys(d, nd, fp, ctx);
-            const real c = real(2.0 * t.D[r][r] * t.invdx[d]);
+            const real c = Tab<real>::dk(t, d, r, 0);
 #pragma unroll
             for (int v = 0; v < M; ++v) R[v] += c * fp[v];
         }
@@ -98,7 +98,7 @@ __device__ __forceinline__ void rhs_lane(const Tables &t, const real *u, const C
 #pragma unroll
             for (int q = 0; q < n1; ++q) {
                 const int qn = line_node<N, DIM>(pd, d, q);
-                const real c = real(t.D[r][q] * t.invdx[d]);
+                const real c = Tab<real>::dn(t, d, r, q);
                 gB += c * lds[(5 + d) * BLK + base + qn];
                 gpsi += c * lds[8 * BLK + base + qn];
             }
@@ -118,8 +118,7 @@ __device__ __forceinline__ void rhs_lane(const Tables &t, const real *u, const C
                 int sd = pd[d] - k;
                 if (sd < 0) sd += n1;
                 const int src = base + line_node<N, DIM>(pd, d, sd);
-                const int qd = pd[d] + n1 - k < n1 ? pd[d] + n1 - k : pd[d] - k;
-                const real c = real(2.0 * t.D[pd[d]][qd] * t.invdx[d]);
+                const real c = Tab<real>::dk(t, d, pd[d], n1 - k);
 #pragma unroll
                 for (int v = 0; v < M; ++v) R[v] += c * xch[((d * NPRIM + (k - 1)) * M + v) * BLK + src];
             }
@@ -183,7 +182,7 @@ __device__ __forceinline__ void rhs_lane(const Tables &t, const real *u, const C
 #pragma unroll
             for (int v = 0; v < M; ++v) jump[v] += ncn[v] - nco[v];
         }
-        const real g = real(side ? t.invw_dx[d][pd[d]] : -t.invw_dx[d][pd[d]]);
+        const real g = side ? Tab<real>::invw(t, d, pd[d]) : -Tab<real>::invw(t, d, pd[d]);
 #pragma unroll
         for (int v = 0; v < M; ++v) R[v] += g * jump[v];
     }
