@@ -521,20 +521,22 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
         constexpr bool W = decltype(walls)::value;
         nb = neighbours<DIM, W>(t, es);
         const real *ts = (const real *)a.traces;
+        // every lane loads (an interior lane a face node of its own element,
+        // a valid address whose value it drops), so that no branch waits
+        // for the loads before the first stage needs them
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            lamd[d] = real(0);
-            if (!onface[d]) continue;
             const int face = 2 * d + side[d], nface = 2 * d + 1 - side[d];
             const int kk = DIM == 1 ? 0 : (d == 0 ? pd[1] : pd[0]);
-            const long en = side[d] ? nb.n[d][1] : nb.n[d][0];
-            const real so = ts[((long)(face * FD::NCT + FD::SPEED) * E + es) * nfn + kk];
             // beyond a wall, the mirror image has the element's own wave speed
             const bool wl = W && ((nb.wall >> face) & 1);
-            const real sn = wl ? so : ts[((long)(nface * FD::NCT + FD::SPEED) * E + en) * nfn + kk];
+            const long en = wl ? es : (side[d] ? nb.n[d][1] : nb.n[d][0]);
+            const int fn = wl ? face : nface;
+            const real so = ts[((long)(face * FD::NCT + FD::SPEED) * E + es) * nfn + kk];
+            const real sn = ts[((long)(fn * FD::NCT + FD::SPEED) * E + en) * nfn + kk];
             real lam = dmax(so, sn);
             if constexpr (EQ == EQ_MHD) lam = dmax(lam, ctx.ch);
-            lamd[d] = lam;
+            lamd[d] = onface[d] ? lam : real(0);
         }
     };
     if (t.wall[0] | t.wall[1]) face_speeds(std::true_type{});
