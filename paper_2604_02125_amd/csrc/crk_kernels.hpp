@@ -566,14 +566,10 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
             double am;
             if (!smooth) {
                 am = a.alpha[tg];
-            } else if (j == 0) {
-                am = a.alpha_raw[tg];
-#pragma unroll
-                for (int d = 0; d < DIM; ++d)
-#pragma unroll
-                    for (int sd = 0; sd < 2; ++sd) am = fmax(am, 0.5 * a.alpha_raw[nb.n[d][sd]]);
-                a.alpha_s[e] = am;
             } else {
+                // the element itself (j = 0) and its face neighbours take the
+                // same path, so that the loads of all these lanes are in
+                // flight together
                 Nbrs nt;
                 if (t.wall[0] | t.wall[1]) nt = neighbours<DIM, true>(t, tg);
                 else nt = neighbours<DIM, false>(t, tg);
@@ -582,6 +578,7 @@ __device__ __forceinline__ void local_tile(const Tables &t, const StepPtrs &a, l
                 for (int d = 0; d < DIM; ++d)
 #pragma unroll
                     for (int sd = 0; sd < 2; ++sd) am = fmax(am, 0.5 * a.alpha_raw[nt.n[d][sd]]);
+                if (j == 0) a.alpha_s[e] = am;
             }
             alds[le * NA + j] = real(am);
         }
