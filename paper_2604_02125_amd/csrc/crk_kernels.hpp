@@ -201,13 +201,12 @@ struct RkPtrs {
 
 // ---------------------------------------------------------------- helpers
 // element coordinates and the four (two in 1D) face neighbours; e < 2^31.
-// The row index comes from a double-precision product with 1/nx (off by at
-// most one next to exact multiples, then corrected): far cheaper per lane
-// than a 64-bit integer division.  A face on a reflective wall has the
-// element itself as neighbour (beyond the wall lies its mirror image, whose
-// blending coefficient and wave speeds are the element's own) and its bit
-// 2d + side set in `wall`: the kernels that read the neighbour's state or
-// face data take the mirror image there instead.
+// The row index comes from the host-formed multiply-and-shift (exact, see
+// Tables::nx_m): far cheaper per lane than an integer division.  A face on
+// a reflective wall has the element itself as neighbour (beyond the wall
+// lies its mirror image, whose blending coefficient and wave speeds are the
+// element's own) and its bit 2d + side set in `wall`: the kernels that read
+// the neighbour's state or face data take the mirror image there instead.
 struct Nbrs {
     long n[2][2];   // [d][side]
     int wall;       // bit 2d + side: that face lies on a wall
