@@ -641,3 +641,42 @@ def test_run_many_steps(orc, case):
         for _ in range(nsteps):
             ref, _ = orc.crk_step(p, ref, orc.compute_dt(p, ref))
         assert _rel(out.cpu().numpy(), ref) <= 1e-11     # 200 steps of per-step round-off
+
+
+def test_indicator_at_the_alpha_min_cutoff(orc):
+    """Raw blending coefficients of elements whose modal energy straddles the
+    point E* where the logistic map of the modal indicator (Section 4, the
+    Hennemann-Gassner form) equals alpha_min.  Element e holds rho = 1, v = 0
+    and p = 1 + a_e phi, phi the orthonormal Legendre polynomial of degree N
+    in x on [0, 1], so that its energy fraction in the highest modes is
+    a_e^2 / (1 + a_e^2); the energies sweep E* (1 -+ 2 %).  Below E* the GPU
+    may skip the logistic map (far enough below it, the coefficient is zero
+    either way); zeros and values must be the oracle's, element by element,
+    on both sides of the point where the skip starts."""
+    N, n = 3, 64
+    p, s = _pair(orc, dim=2, nx=n, ny=n, N=N, vol_flux=1, limiter=orc.LIM_BLEND_MODAL, alpha_max=0.008,
+                 alpha_min=1e-3)
+    thr = 0.5 * 10.0 ** (-1.8 * (N + 1) ** 0.25)
+    sharp = np.log((1.0 - 1e-4) / 1e-4)
+    e_star = thr - np.log(1.0 / p.alpha_min - 1.0) * thr / sharp
+    E = n * n
+    energy = e_star * (1.0 + np.linspace(-0.02, 0.02, E))
+    amp = np.sqrt(energy / (1.0 - energy))
+    xi, _ = orc.gll(N)
+    phi = np.sqrt(2.0 * N + 1.0) * np.polynomial.legendre.legval(2.0 * xi - 1.0, [0.0] * N + [1.0])
+    phi_nodes = np.tile(phi, N + 1)                     # node j (N+1) + i takes phi(xi_i)
+    u = np.zeros((4, E, (N + 1) ** 2))
+    u[0] = 1.0
+    u[3] = (1.0 + amp[:, None] * phi_nodes[None, :]) / (p.gamma - 1.0)
+    araw_o, _, _ = orc.indicator(p, u)
+    araw_g = s.indicator(torch.tensor(u, device="cuda"))[0].cpu().numpy()
+    # the sweep covers the three regimes: far enough below E* (skippable),
+    # just below it (full evaluation, zero) and above it (alpha >= alpha_min)
+    skip_from = e_star - 1e-3 * thr
+    assert (energy < skip_from - 1e-3 * e_star).sum() > 100
+    assert ((energy > skip_from + 1e-4 * e_star) & (energy < e_star * (1 - 1e-4))).sum() > 100
+    assert (energy > e_star * (1 + 1e-4)).sum() > 100
+    assert np.all(araw_o[energy < e_star * (1 - 1e-4)] == 0.0)
+    assert np.all(araw_o[energy > e_star * (1 + 1e-4)] >= p.alpha_min)
+    assert np.array_equal(araw_g == 0.0, araw_o == 0.0)
+    assert np.max(np.abs(araw_g - araw_o)) <= 1e-13
