@@ -563,6 +563,29 @@ def variant_rkfr(crk, inputs, orc, steps, warmup, threads, err=True):
     return out
 
 
+def variant_sizes(crk, inputs, sizes=(128, 256, 512, 1024, 2048)):
+    """The headline workload's pipelined step against mesh size, FP64 and
+    FP32 (run only when asked for by name: the 2048^2 meshes take a while)."""
+    import torch
+    xi, _, _ = crk.reference_element(3)
+    rows = {}
+    for prec in (crk.FP64, crk.FP32):
+        for n in sizes:
+            s = crk.Solver(nx=n, ny=n, precision=prec, **KHI)
+            pipe = Pipelined(s, inputs.kelvin_helmholtz(n, n, xi))
+            steps = max(10, min(200, int(200 * (256 / n) ** 2)))
+            _, kt = timed(pipe, steps, 3, events=True)
+            el = min(timed(pipe, steps, 2)[0] for _ in range(2))
+            dofs = n * n * 16
+            rows[f"{'fp64' if prec == crk.FP64 else 'fp32'}_{n}x{n}"] = {
+                "value": dofs * steps / el, "unit": "DOF-updates/s", "ms_per_step": el / steps * 1e3,
+                "k_local_plain_ms": kt["k_local_plain_ms"], "interface_ms": kt.get("interface_ms"),
+                "state_bytes": 4 * dofs * (8 if prec == crk.FP64 else 4)}
+            del pipe, s
+            torch.cuda.empty_cache()
+    return {"workload": "2D Euler Kelvin-Helmholtz, N=3, Kennedy-Gruber, blending, pipelined step", "sizes": rows}
+
+
 def variant_crash_study(crk):
     """Section 4.2's robustness claim on the paper's own mesh: KHI 64^2, N=3,
     blending with alpha_max = 0.008, to t = 15, for the central (plain FR
@@ -731,6 +754,8 @@ def main():
             v["khi256_crkfr_vs_rkfr"] = variant_rkfr(crk, inputs, orc, 20, 2, threads, err=args.err_steps > 0)
         if want("khi64_crash_study"):
             v["khi64_crash_study"] = variant_crash_study(crk)
+        if only is not None and "khi_size_sweep" in only:
+            v["khi_size_sweep"] = variant_sizes(crk, inputs)
         v["_note"] = ("l2_rel_error_vs_fp64_oracle = ||u_gpu - u_oracle||_2 / ||u_oracle||_2 and "
                       "linf_rel_error_vs_fp64_oracle = max|u_gpu - u_oracle| / max|u_oracle| over all values "
                       "after error_after_steps steps from the same initial state (the FP64 rows are a "
