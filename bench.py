@@ -649,6 +649,8 @@ def main():
     # grid: profiler runs skip them so that per-kernel averages cover the headline
     ap.add_argument("--no-blended", action="store_true")
     ap.add_argument("--only", default=None, help="comma-separated variant names to run (profiling)")
+    ap.add_argument("--sizes", default="128,256,512,1024,2048",
+                    help="mesh sizes of the khi_size_sweep variant (comma-separated n for n x n)")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--cpu-steps-single", type=int, default=2)
     ap.add_argument("--err-steps", type=int, default=3)
@@ -755,7 +757,7 @@ def main():
         if want("khi64_crash_study"):
             v["khi64_crash_study"] = variant_crash_study(crk)
         if only is not None and "khi_size_sweep" in only:
-            v["khi_size_sweep"] = variant_sizes(crk, inputs)
+            v["khi_size_sweep"] = variant_sizes(crk, inputs, tuple(int(x) for x in args.sizes.split(",")))
         v["_note"] = ("l2_rel_error_vs_fp64_oracle = ||u_gpu - u_oracle||_2 / ||u_oracle||_2 and "
                       "linf_rel_error_vs_fp64_oracle = max|u_gpu - u_oracle| / max|u_oracle| over all values "
                       "after error_after_steps steps from the same initial state (the FP64 rows are a "
